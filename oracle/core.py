@@ -1,0 +1,201 @@
+"""Oracle: Python driver of the plain-C KFVM-WENO right-hand side (kfvm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline leg
+of the benchmark may import this module; the product path never does.
+
+`Oracle(d, R, n, dx, gamma, ...)` holds the tables of oracle.weights and exposes
+rhs / step / states / rhs_cells / cfl_dt / riemann on numpy float64 arrays laid
+out as U[v][z][y][x] (2D: U[v][y][x]).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from . import weights as _w
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kfvm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+EPS_WENO = 1e-40   # epsilon of the nonlinear weights (section 3.3)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Ctx(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("R", C.c_int), ("nvar", C.c_int),
+        ("n", C.c_int * 3), ("dx", C.c_double * 3), ("gamma", C.c_double),
+        ("n0", C.c_int), ("s0", C.POINTER(C.c_int)), ("nst", C.c_int),
+        ("mem_ptr", C.POINTER(C.c_int)), ("mem", C.POINTER(C.c_int)),
+        ("w_ptr", C.POINTER(C.c_int)), ("w", C.POINTER(C.c_double)),
+        ("lin_w", C.POINTER(C.c_double)), ("n_pts", C.c_int), ("n_der", C.c_int),
+        ("gl_w", C.POINTER(C.c_double)), ("eps", C.c_double),
+        ("limiter", C.c_int), ("kappa", C.c_double), ("riemann", C.c_int),
+        ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER
+        for name, args in [
+            ("oracle_states", [P(_Ctx), P(C.c_double), P(C.c_double)]),
+            ("oracle_rhs", [P(_Ctx), P(C.c_double), P(C.c_double)]),
+            ("oracle_rhs_cells", [P(_Ctx), P(C.c_double), C.c_long, P(C.c_long), P(C.c_double)]),
+            ("oracle_step", [P(_Ctx), P(C.c_double), C.c_double]),
+            ("oracle_cfl_dt", [P(_Ctx), P(C.c_double), C.c_double, P(C.c_double)]),
+        ]:
+            f = getattr(_lib, name)
+            f.argtypes, f.restype = args, C.c_int
+        _lib.oracle_riemann.argtypes = [P(_Ctx), C.c_long, P(C.c_double), P(C.c_double), C.c_int,
+                                        P(C.c_double)]
+        _lib.oracle_riemann.restype = None
+        _lib.oracle_phi.argtypes = [P(_Ctx), P(C.c_double), P(C.c_double), P(C.c_double)]
+        _lib.oracle_phi.restype = None
+    return _lib
+
+
+def _ptr(a, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """Plain CPU KFVM-WENO on a periodic box of n cells per axis."""
+
+    def __init__(self, d: int, R: int, n, dx=None, gamma: float = 1.4, *, limiter: bool = True,
+                 kappa: float = 0.5, riemann: str = "hllc", weno: bool = True, tables=None):
+        self.d, self.R = d, R
+        self.nvar = d + 2
+        n = list(n) + [1] * (3 - len(n))
+        dx = list(dx) if dx is not None else [1.0 / n[a] for a in range(d)]
+        dx = dx + [1.0] * (3 - len(dx))
+        self.shape = tuple(reversed(n[:d]))        # numpy spatial shape (z, y, x)
+        self.ncell = int(np.prod(n))
+        T = tables if tables is not None else _w.tables(d, R)
+        self.tables = T
+        keep = []
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(np.asarray(x, dtype=dt))
+            keep.append(a)
+            return a
+
+        s0 = arr(T["s0"].reshape(-1), np.int32)
+        mem = arr(np.concatenate(T["members"]), np.int32)
+        mem_ptr = arr(np.concatenate([[0], np.cumsum([len(m) for m in T["members"]])]), np.int32)
+        w = arr(np.concatenate([x.reshape(-1) for x in T["weights"]]), np.float64)
+        w_ptr = arr(np.concatenate([[0], np.cumsum([x.size for x in T["weights"]])[:-1]]), np.int32)
+        lin_w = arr(T["gamma"], np.float64)
+        gl_w = arr(T["gl_weights"], np.float64)
+        self._keep = keep
+        ctx = _Ctx()
+        ctx.dim, ctx.R, ctx.nvar = d, R, self.nvar
+        ctx.n[:] = n
+        ctx.dx[:] = dx
+        ctx.gamma = gamma
+        ctx.n0 = len(T["s0"])
+        ctx.s0 = _ptr(s0, C.c_int)
+        ctx.nst = len(T["members"])
+        ctx.mem_ptr, ctx.mem = _ptr(mem_ptr, C.c_int), _ptr(mem, C.c_int)
+        ctx.w_ptr, ctx.w = _ptr(w_ptr, C.c_int), _ptr(w)
+        ctx.lin_w = _ptr(lin_w)
+        ctx.n_pts, ctx.n_der = T["n_pts"], T["n_der"]
+        ctx.gl_w = _ptr(gl_w)
+        ctx.eps = EPS_WENO
+        ctx.limiter, ctx.kappa = int(limiter), kappa
+        ctx.riemann = {"hllc": 0, "hll": 1}[riemann]
+        ctx.weno = int(weno)
+        ctx.flags = C.POINTER(C.c_uint8)()
+        self._ctx = ctx
+        self._lib = _load()
+
+    # -- helpers ------------------------------------------------------------
+    def _check_U(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        if U.shape != (self.nvar,) + self.shape:
+            raise ValueError(f"U must have shape {(self.nvar,) + self.shape}, got {U.shape}")
+        return U
+
+    def _call(self, rc):
+        if rc != 0:
+            raise OracleError(f"oracle returned {rc}")
+
+    def set_flags(self, flags):
+        """Replay gate decisions: flags[v][cells] = 1 for WENO, 0 for the linear S0 value."""
+        if flags is None:
+            self._flags = None
+            self._ctx.flags = C.POINTER(C.c_uint8)()
+            return
+        f = np.ascontiguousarray(flags, dtype=np.uint8).reshape(self.nvar, self.ncell)
+        self._flags = f
+        self._ctx.flags = _ptr(f, C.c_uint8)
+
+    # -- the method ---------------------------------------------------------
+    def rhs(self, U):
+        U = self._check_U(U)
+        out = np.empty_like(U)
+        self._call(self._lib.oracle_rhs(C.byref(self._ctx), _ptr(U), _ptr(out)))
+        return out
+
+    def states(self, U):
+        """Riemann states after the limiter: [cells, n_pts, nvar] (conserved variables)."""
+        U = self._check_U(U)
+        out = np.empty((self.ncell, self.tables["n_pts"], self.nvar))
+        self._call(self._lib.oracle_states(C.byref(self._ctx), _ptr(U), _ptr(out)))
+        return out
+
+    def rhs_cells(self, U, cells):
+        U = self._check_U(U)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty((len(cells), self.nvar))
+        self._call(self._lib.oracle_rhs_cells(C.byref(self._ctx), _ptr(U), len(cells),
+                                              _ptr(cells, C.c_long), _ptr(out)))
+        return out
+
+    def step(self, U, dt):
+        U = self._check_U(U).copy()
+        self._call(self._lib.oracle_step(C.byref(self._ctx), _ptr(U), float(dt)))
+        return U
+
+    def cfl_dt(self, U, cfl):
+        U = self._check_U(U)
+        dt = C.c_double()
+        self._call(self._lib.oracle_cfl_dt(C.byref(self._ctx), _ptr(U), float(cfl), C.byref(dt)))
+        return dt.value
+
+    def riemann(self, uL, uR, axis):
+        uL = np.ascontiguousarray(uL, dtype=np.float64).reshape(-1, self.nvar)
+        uR = np.ascontiguousarray(uR, dtype=np.float64).reshape(-1, self.nvar)
+        F = np.empty_like(uL)
+        self._lib.oracle_riemann(C.byref(self._ctx), len(uL), _ptr(uL), _ptr(uR), int(axis), _ptr(F))
+        return F
+
+    def phi(self, ref):
+        """(Phi, Phi^-1) of the linearised primitive variables at a reference state."""
+        ref = np.ascontiguousarray(ref, dtype=np.float64)
+        A = np.empty((self.nvar, self.nvar))
+        B = np.empty((self.nvar, self.nvar))
+        self._lib.oracle_phi(C.byref(self._ctx), _ptr(ref), _ptr(A), _ptr(B))
+        return A, B

@@ -1,0 +1,489 @@
+/*
+ * Oracle: KFVM-WENO right-hand side, positivity limiter, Riemann solvers and
+ * SSP-RK3 step for the compressible Euler equations on a periodic uniform
+ * Cartesian grid, in plain binary64 C.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link or call this
+ * library; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code with the GPU library.
+ *
+ * It follows the paper's order of operations (section 5.3 "Time advancement"):
+ * for every cell
+ *   1. periodic ghost cells (index wrap);
+ *   2. Riemann states: the transformation matrix Phi of the linearised
+ *      primitive variables from the cell's own average (section 3.4.2,
+ *      eq. consToLPMat), W_h = Phi U_h over S0 (eq. consToRecVar), per
+ *      component and per (sub)stencil the point values r.g and derivative
+ *      values (eq. reconVec), the smoothness indicators (eq. smoothIndic, with no
+ *      extra grid factor), the WENO-JS form weights (eq. nlinWts, eps = 1e-40),
+ *      the WENO-AO blend (eq. wenoAOrec), then u_s = Phi^-1 w_s
+ *      (eq. recVarToCons, eq. lpToConsMat);
+ *   3. the positivity limiter of section 4 (density scaling eq. ppThetaRho and
+ *      eq. ppCorrectDens, pressure scaling by bisection eq. thetapRoot, eq. thetaP
+ *      and eq. ppCorrectPres), with the flattener eta = 0 and kappa a parameter;
+ *   5. an approximate Riemann solver at every face Gauss point: HLLC (Toro,
+ *      "Riemann Solvers and Numerical Methods for Fluid Dynamics", ch. 10) or HLL
+ *      (Harten, Lax and van Leer 1983), with the wavespeed estimates of Batten et
+ *      al. (1997) from Roe averages (section 6);
+ *   6. Gauss-Legendre face integral of the fluxes and the flux difference.
+ * The time step is the three-stage SSP Runge-Kutta method of Shu and Osher
+ * (1988).  Its stages are written out literally.
+ *
+ * Data layout: U[v][z][y][x] with x fastest (struct of arrays); 2D grids have
+ * nz = 1 and 4 variables (rho, rho u, rho v, E), 3D grids 5 (rho, rho u, rho v,
+ * rho w, E).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXD 3
+#define MAXV 5
+#define MAXST 8
+
+enum { OK = 0, ERR_ARG = -1, ERR_NONPHYSICAL = -3 };
+
+typedef struct {
+    int dim, R, nvar;
+    int n[3];              /* cells per axis; n[2] = 1 in 2D */
+    double dx[3];          /* grid spacing per axis */
+    double gamma;          /* ratio of specific heats */
+    int n0;                /* |S0| */
+    const int *s0;         /* [n0][dim] unit-cell offsets of S0 */
+    int nst;               /* number of (sub)stencils: 2 + 2 dim */
+    const int *mem_ptr;    /* [nst + 1] start of each member list in mem */
+    const int *mem;        /* member indices into S0 */
+    const int *w_ptr;      /* [nst] start of each stencil's table in w */
+    const double *w;       /* row-major tables [n_pts + n_der][N_q] */
+    const double *lin_w;   /* [nst] linear weights gamma_q */
+    int n_pts, n_der;      /* face points per cell, derivative rows */
+    const double *gl_w;    /* [R] Gauss-Legendre weights on [-1/2, 1/2], summing to 1 */
+    double eps;            /* epsilon of the nonlinear weights */
+    int limiter;           /* 0: off, 1: on */
+    double kappa;          /* bound widening of the limiter */
+    int riemann;           /* 0: HLLC, 1: HLL */
+    int weno;              /* 1: WENO-AO; 0: linear S0 reconstruction only */
+    const uint8_t *flags;  /* optional [nvar][cells]: 1 = WENO, 0 = linear (gate replay) */
+} oracle_ctx;
+
+/* ---------------------------------------------------------------- grid --- */
+static long ncells(const oracle_ctx *c) { return (long)c->n[0] * c->n[1] * c->n[2]; }
+
+static long wrap_index(const oracle_ctx *c, long cell, const int *off)
+{
+    long i = cell % c->n[0], j = (cell / c->n[0]) % c->n[1], k = cell / ((long)c->n[0] * c->n[1]);
+    long o[3] = {0, 0, 0};
+    for (int a = 0; a < c->dim; ++a) o[a] = off[a];
+    i = ((i + o[0]) % c->n[0] + c->n[0]) % c->n[0];
+    j = ((j + o[1]) % c->n[1] + c->n[1]) % c->n[1];
+    k = ((k + o[2]) % c->n[2] + c->n[2]) % c->n[2];
+    return i + c->n[0] * (j + c->n[1] * k);
+}
+
+static void load_cell(const oracle_ctx *c, const double *U, long cell, double *u)
+{
+    long N = ncells(c);
+    for (int v = 0; v < c->nvar; ++v) u[v] = U[v * N + cell];
+}
+
+/* ----------------------------------------------------------------- EOS --- */
+/* p = (gamma - 1) (E - rho |u|^2 / 2) (section 1, eq. euler) */
+static double pressure(const oracle_ctx *c, const double *u)
+{
+    double ke = 0.0;
+    for (int a = 0; a < c->dim; ++a) ke += u[1 + a] * u[1 + a];
+    ke = 0.5 * ke / u[0];
+    return (c->gamma - 1.0) * (u[c->dim + 1] - ke);
+}
+
+static int admissible(const oracle_ctx *c, const double *u)
+{
+    for (int v = 0; v < c->nvar; ++v)
+        if (!isfinite(u[v])) return 0;
+    return u[0] > 0.0 && pressure(c, u) > 0.0;
+}
+
+/* ----------------------------------------- linearised primitive variables --- */
+/* Phi = dV/dU at the reference state (eq. consToLPMat); in 2D the u_3 row and
+ * column are dropped.  Dense nvar x nvar matrices, row-major. */
+static void phi_matrices(const oracle_ctx *c, const double *ref, double *Phi, double *Phi_inv)
+{
+    int d = c->dim, nv = c->nvar, e = d + 1;
+    double g = c->gamma, rho = ref[0], u[MAXD], uu = 0.0;
+    for (int a = 0; a < d; ++a) { u[a] = ref[1 + a] / rho; uu += u[a] * u[a]; }
+    memset(Phi, 0, sizeof(double) * nv * nv);
+    memset(Phi_inv, 0, sizeof(double) * nv * nv);
+    Phi[0 * nv + 0] = 1.0;
+    for (int a = 0; a < d; ++a) {
+        Phi[(1 + a) * nv + 0] = -u[a] / rho;
+        Phi[(1 + a) * nv + 1 + a] = 1.0 / rho;
+        Phi[e * nv + 1 + a] = (1.0 - g) * u[a];
+    }
+    Phi[e * nv + 0] = (g - 1.0) * uu / 2.0;
+    Phi[e * nv + e] = g - 1.0;
+    /* Phi^-1 = dU/dV (eq. primMat).  The energy row holds dE/du_i = rho u_i:
+     * the matrix printed as eq. lpToConsMat shows u_i there, which is not the
+     * inverse of eq. consToLPMat; the definition as the exact inverse wins. */
+    Phi_inv[0 * nv + 0] = 1.0;
+    for (int a = 0; a < d; ++a) {
+        Phi_inv[(1 + a) * nv + 0] = u[a];
+        Phi_inv[(1 + a) * nv + 1 + a] = rho;
+        Phi_inv[e * nv + 1 + a] = rho * u[a];
+    }
+    Phi_inv[e * nv + 0] = uu / 2.0;
+    Phi_inv[e * nv + e] = 1.0 / (g - 1.0);
+}
+
+static void matvec(int nv, const double *A, const double *x, double *y)
+{
+    for (int i = 0; i < nv; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) s += A[i * nv + j] * x[j];
+        y[i] = s;
+    }
+}
+
+/* --------------------------------------------- Riemann states of one cell --- */
+/* states: [n_pts][nvar].  Returns OK or ERR_NONPHYSICAL. */
+static int cell_states(const oracle_ctx *c, const double *U, long cell, double *states)
+{
+    int nv = c->nvar, n0 = c->n0, np = c->n_pts, nd = c->n_der;
+    long N = ncells(c);
+    double ref[MAXV], Phi[MAXV * MAXV], Phi_inv[MAXV * MAXV];
+    load_cell(c, U, cell, ref);
+    if (!admissible(c, ref)) return ERR_NONPHYSICAL;
+    phi_matrices(c, ref, Phi, Phi_inv);
+
+    /* W_h = Phi U_h over S0 (eq. consToRecVar) */
+    double *W = (double *)malloc(sizeof(double) * n0 * nv);
+    for (int h = 0; h < n0; ++h) {
+        double uh[MAXV];
+        load_cell(c, U, wrap_index(c, cell, c->s0 + h * c->dim), uh);
+        matvec(nv, Phi, uh, W + h * nv);
+    }
+
+    double *wpt = (double *)malloc(sizeof(double) * np * nv);   /* w_s in W variables */
+    double *vals = (double *)malloc(sizeof(double) * MAXST * np);
+    for (int k = 0; k < nv; ++k) {
+        double beta[MAXST], om[MAXST];
+        for (int q = 0; q < c->nst; ++q) {
+            int Nq = c->mem_ptr[q + 1] - c->mem_ptr[q];
+            const int *mem = c->mem + c->mem_ptr[q];
+            const double *tab = c->w + c->w_ptr[q];
+            /* point values: one dot product per target (eq. reconVec) */
+            for (int s = 0; s < np; ++s) {
+                double acc = 0.0;
+                for (int j = 0; j < Nq; ++j) acc += tab[s * Nq + j] * W[mem[j] * nv + k];
+                vals[q * np + s] = acc;
+            }
+            /* smoothness indicator: sum of squared derivative values (eq. smoothIndic) */
+            double b = 0.0;
+            for (int a = 0; a < nd; ++a) {
+                double acc = 0.0;
+                for (int j = 0; j < Nq; ++j) acc += tab[(np + a) * Nq + j] * W[mem[j] * nv + k];
+                b += acc * acc;
+            }
+            beta[q] = b;
+        }
+        int use_weno = c->weno;
+        if (c->flags) use_weno = c->flags[(long)k * N + cell] != 0;
+        if (!use_weno) {
+            for (int s = 0; s < np; ++s) wpt[s * nv + k] = vals[0 * np + s];
+            continue;
+        }
+        /* nonlinear weights (eq. nlinWts) */
+        double sum = 0.0;
+        for (int q = 0; q < c->nst; ++q) {
+            om[q] = c->lin_w[q] / (beta[q] * beta[q] + c->eps);
+            sum += om[q];
+        }
+        for (int q = 0; q < c->nst; ++q) om[q] /= sum;
+        /* WENO-AO blend (eq. wenoAOrec) */
+        for (int s = 0; s < np; ++s) {
+            double f = om[0] / c->lin_w[0] * vals[0 * np + s];
+            for (int q = 1; q < c->nst; ++q)
+                f += (om[q] - om[0] * c->lin_w[q] / c->lin_w[0]) * vals[q * np + s];
+            wpt[s * nv + k] = f;
+        }
+    }
+    /* back to conserved variables (eq. recVarToCons) */
+    for (int s = 0; s < np; ++s) matvec(nv, Phi_inv, wpt + s * nv, states + s * nv);
+    free(W);
+    free(wpt);
+    free(vals);
+
+    if (!c->limiter) return OK;
+
+    /* ------------------------------------ positivity limiter (section 4) --- */
+    double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+    int lo[3] = {-1, -1, -1}, hi[3] = {1, 1, 1};
+    if (c->dim < 3) lo[2] = hi[2] = 0;
+    for (int dz = lo[2]; dz <= hi[2]; ++dz)
+        for (int dy = lo[1]; dy <= hi[1]; ++dy)
+            for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+                int off[3] = {dx, dy, dz};
+                double un[MAXV];
+                load_cell(c, U, wrap_index(c, cell, off), un);
+                if (!admissible(c, un)) return ERR_NONPHYSICAL;
+                double pn = pressure(c, un);
+                if (un[0] > rmax) rmax = un[0];
+                if (un[0] < rmin) rmin = un[0];
+                if (pn < pmin) pmin = pn;
+            }
+    /* widened bounds with the flattener eta = 0 */
+    rmax *= 1.0 + c->kappa;
+    rmin *= 1.0 - c->kappa;
+    pmin *= 1.0 - c->kappa;
+
+    /* density scaling (eq. ppThetaRho): only the violated side of each bound */
+    double th = 1.0;
+    for (int s = 0; s < np; ++s) {
+        double rs = states[s * nv + 0];
+        if (rs < rmin) {
+            double t = (ref[0] - rmin) / (ref[0] - rs);
+            if (t < th) th = t;
+        } else if (rs > rmax) {
+            double t = (rmax - ref[0]) / (rs - ref[0]);
+            if (t < th) th = t;
+        }
+    }
+    if (th < 1.0)
+        for (int s = 0; s < np; ++s)
+            for (int v = 0; v < nv; ++v)
+                states[s * nv + v] = ref[v] + th * (states[s * nv + v] - ref[v]);   /* eq. ppCorrectDens */
+
+    /* pressure scaling (eq. thetapRoot, eq. thetaP) by 60 bisection steps */
+    double thp = 1.0;
+    for (int s = 0; s < np; ++s) {
+        if (pressure(c, states + s * nv) >= pmin) continue;
+        double a = 0.0, b = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double m = 0.5 * (a + b), um[MAXV];
+            for (int v = 0; v < nv; ++v) um[v] = ref[v] + m * (states[s * nv + v] - ref[v]);
+            if (pressure(c, um) >= pmin) a = m; else b = m;
+        }
+        if (a < thp) thp = a;
+    }
+    if (thp < 1.0)
+        for (int s = 0; s < np; ++s)
+            for (int v = 0; v < nv; ++v)
+                states[s * nv + v] = ref[v] + thp * (states[s * nv + v] - ref[v]);  /* eq. ppCorrectPres */
+    return OK;
+}
+
+/* ----------------------------------------------------- Riemann solvers --- */
+static void phys_flux(const oracle_ctx *c, const double *u, int a, double p, double *F)
+{
+    int d = c->dim, e = d + 1;
+    double un = u[1 + a] / u[0];
+    F[0] = u[1 + a];
+    for (int b = 0; b < d; ++b) F[1 + b] = u[1 + b] * un + (b == a ? p : 0.0);
+    F[e] = un * (u[e] + p);
+}
+
+/* Numerical flux across a face with normal axis a; uL on the lower side. */
+static void riemann(const oracle_ctx *c, const double *uL, const double *uR, int a, double *F)
+{
+    int d = c->dim, nv = c->nvar, e = d + 1;
+    double g = c->gamma;
+    double pL = pressure(c, uL), pR = pressure(c, uR);
+    double rL = uL[0], rR = uR[0];
+    double vL[MAXD], vR[MAXD], qL = 0.0, qR = 0.0;
+    for (int b = 0; b < d; ++b) {
+        vL[b] = uL[1 + b] / rL; vR[b] = uR[1 + b] / rR;
+        qL += vL[b] * vL[b]; qR += vR[b] * vR[b];
+    }
+    double cL = sqrt(g * pL / rL), cR = sqrt(g * pR / rR);
+    double HL = (uL[e] + pL) / rL, HR = (uR[e] + pR) / rR;
+    /* Roe averages for the Batten et al. wavespeeds */
+    double sL = sqrt(rL), sR = sqrt(rR), vt[MAXD], qt = 0.0;
+    for (int b = 0; b < d; ++b) { vt[b] = (sL * vL[b] + sR * vR[b]) / (sL + sR); qt += vt[b] * vt[b]; }
+    double Ht = (sL * HL + sR * HR) / (sL + sR);
+    double ct = sqrt((g - 1.0) * (Ht - 0.5 * qt));
+    double SL = fmin(vL[a] - cL, vt[a] - ct);
+    double SR = fmax(vR[a] + cR, vt[a] + ct);
+    double FL[MAXV], FR[MAXV];
+    phys_flux(c, uL, a, pL, FL);
+    phys_flux(c, uR, a, pR, FR);
+
+    if (c->riemann == 1) {   /* HLL */
+        if (SL >= 0.0) { memcpy(F, FL, sizeof(double) * nv); return; }
+        if (SR <= 0.0) { memcpy(F, FR, sizeof(double) * nv); return; }
+        for (int v = 0; v < nv; ++v)
+            F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) / (SR - SL);
+        return;
+    }
+    /* HLLC */
+    if (SL >= 0.0) { memcpy(F, FL, sizeof(double) * nv); return; }
+    if (SR <= 0.0) { memcpy(F, FR, sizeof(double) * nv); return; }
+    double Ss = (pR - pL + rL * vL[a] * (SL - vL[a]) - rR * vR[a] * (SR - vR[a]))
+              / (rL * (SL - vL[a]) - rR * (SR - vR[a]));
+    const double *uK = Ss >= 0.0 ? uL : uR;
+    const double *FK = Ss >= 0.0 ? FL : FR;
+    double SK = Ss >= 0.0 ? SL : SR, rK = Ss >= 0.0 ? rL : rR, pK = Ss >= 0.0 ? pL : pR;
+    const double *vK = Ss >= 0.0 ? vL : vR;
+    double fac = rK * (SK - vK[a]) / (SK - Ss), us[MAXV];
+    us[0] = fac;
+    for (int b = 0; b < d; ++b) us[1 + b] = fac * (b == a ? Ss : vK[b]);
+    us[e] = fac * (uK[e] / rK + (Ss - vK[a]) * (Ss + pK / (rK * (SK - vK[a]))));
+    for (int v = 0; v < nv; ++v) F[v] = FK[v] + SK * (us[v] - uK[v]);
+}
+
+/* Gauss-Legendre tensor weight of transverse index g on a face with normal a */
+static double face_weight(const oracle_ctx *c, int g)
+{
+    double w = 1.0;
+    for (int t = 0; t < c->dim - 1; ++t) {
+        w *= c->gl_w[g % c->R];
+        g /= c->R;
+    }
+    return w;
+}
+
+/* Face-averaged flux through the upper face (normal a) of `cell`, from the
+ * Riemann states of the cell (upper side) and its upper neighbour (lower side). */
+static void face_flux(const oracle_ctx *c, const double *st_lo, const double *st_hi, int a, double *Fbar)
+{
+    int nv = c->nvar, ng = c->n_pts / (2 * c->dim);
+    for (int v = 0; v < nv; ++v) Fbar[v] = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        const double *uL = st_lo + ((2 * a + 1) * ng + g) * nv;   /* upper face of the lower cell */
+        const double *uR = st_hi + ((2 * a + 0) * ng + g) * nv;   /* lower face of the upper cell */
+        double F[MAXV];
+        riemann(c, uL, uR, a, F);
+        double w = face_weight(c, g);
+        for (int v = 0; v < nv; ++v) Fbar[v] += w * F[v];
+    }
+}
+
+/* ----------------------------------------------------------- exported --- */
+/* All Riemann states: states[cell][n_pts][nvar]. */
+int oracle_states(const oracle_ctx *c, const double *U, double *states)
+{
+    long N = ncells(c);
+    int err = OK;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long cell = 0; cell < N; ++cell) {
+        int e = cell_states(c, U, cell, states + cell * c->n_pts * c->nvar);
+        if (e != OK) {
+#pragma omp atomic write
+            err = e;
+        }
+    }
+    return err;
+}
+
+/* dU/dt on the whole grid (section 5.3, steps 1-6). */
+int oracle_rhs(const oracle_ctx *c, const double *U, double *dUdt)
+{
+    long N = ncells(c);
+    int nv = c->nvar, np = c->n_pts;
+    double *st = (double *)malloc(sizeof(double) * N * np * nv);
+    if (!st) return ERR_ARG;
+    int err = oracle_states(c, U, st);
+    if (err != OK) { free(st); return err; }
+#pragma omp parallel for schedule(static)
+    for (long cell = 0; cell < N; ++cell) {
+        double acc[MAXV] = {0};
+        for (int a = 0; a < c->dim; ++a) {
+            int up[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
+            up[a] = 1; dn[a] = -1;
+            long cu = wrap_index(c, cell, up), cd = wrap_index(c, cell, dn);
+            double Fp[MAXV], Fm[MAXV];
+            face_flux(c, st + cell * np * nv, st + cu * np * nv, a, Fp);
+            face_flux(c, st + cd * np * nv, st + cell * np * nv, a, Fm);
+            for (int v = 0; v < nv; ++v) acc[v] -= (Fp[v] - Fm[v]) / c->dx[a];
+        }
+        for (int v = 0; v < nv; ++v) dUdt[v * N + cell] = acc[v];
+    }
+    free(st);
+    return OK;
+}
+
+/* dU/dt at a list of cells only, for spot checks on grids too large for the
+ * whole-grid routine.  out: [count][nvar]. */
+int oracle_rhs_cells(const oracle_ctx *c, const double *U, long count, const long *cells, double *out)
+{
+    int nv = c->nvar, np = c->n_pts, err = OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < count; ++i) {
+        long cell = cells[i];
+        double *st = (double *)malloc(sizeof(double) * np * nv * 3);
+        double acc[MAXV] = {0};
+        int e = cell_states(c, U, cell, st);
+        for (int a = 0; a < c->dim && e == OK; ++a) {
+            int up[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
+            up[a] = 1; dn[a] = -1;
+            e = cell_states(c, U, wrap_index(c, cell, up), st + np * nv);
+            if (e == OK) e = cell_states(c, U, wrap_index(c, cell, dn), st + 2 * np * nv);
+            if (e != OK) break;
+            double Fp[MAXV], Fm[MAXV];
+            face_flux(c, st, st + np * nv, a, Fp);
+            face_flux(c, st + 2 * np * nv, st, a, Fm);
+            for (int v = 0; v < nv; ++v) acc[v] -= (Fp[v] - Fm[v]) / c->dx[a];
+        }
+        if (e != OK) {
+#pragma omp atomic write
+            err = e;
+        }
+        for (int v = 0; v < nv; ++v) out[i * nv + v] = acc[v];
+        free(st);
+    }
+    return err;
+}
+
+/* One SSP-RK3 step (Shu-Osher form), U updated in place. */
+int oracle_step(const oracle_ctx *c, double *U, double dt)
+{
+    long M = ncells(c) * c->nvar;
+    double *L = (double *)malloc(sizeof(double) * M);
+    double *U1 = (double *)malloc(sizeof(double) * M);
+    double *U2 = (double *)malloc(sizeof(double) * M);
+    int err = oracle_rhs(c, U, L);
+    if (err == OK) {
+        for (long i = 0; i < M; ++i) U1[i] = U[i] + dt * L[i];
+        err = oracle_rhs(c, U1, L);
+    }
+    if (err == OK) {
+        for (long i = 0; i < M; ++i) U2[i] = 0.75 * U[i] + 0.25 * (U1[i] + dt * L[i]);
+        err = oracle_rhs(c, U2, L);
+    }
+    if (err == OK)
+        for (long i = 0; i < M; ++i) U[i] = U[i] / 3.0 + 2.0 / 3.0 * (U2[i] + dt * L[i]);
+    free(L);
+    free(U1);
+    free(U2);
+    return err;
+}
+
+/* dt = cfl / max_cell sum_a (|u_a| + c_s) / dx_a */
+int oracle_cfl_dt(const oracle_ctx *c, const double *U, double cfl, double *dt)
+{
+    long N = ncells(c);
+    double m = 0.0;
+    int err = OK;
+    for (long cell = 0; cell < N; ++cell) {
+        double u[MAXV];
+        load_cell(c, U, cell, u);
+        if (!admissible(c, u)) { err = ERR_NONPHYSICAL; continue; }
+        double cs = sqrt(c->gamma * pressure(c, u) / u[0]), s = 0.0;
+        for (int a = 0; a < c->dim; ++a) s += (fabs(u[1 + a] / u[0]) + cs) / c->dx[a];
+        if (s > m) m = s;
+    }
+    *dt = cfl / m;
+    return err;
+}
+
+/* Riemann solver on single state pairs, for unit tests: uL, uR, F are [count][nvar]. */
+void oracle_riemann(const oracle_ctx *c, long count, const double *uL, const double *uR, int axis, double *F)
+{
+    for (long i = 0; i < count; ++i)
+        riemann(c, uL + i * c->nvar, uR + i * c->nvar, axis, F + i * c->nvar);
+}
+
+/* Phi and Phi^-1 at a reference state, for unit tests. */
+void oracle_phi(const oracle_ctx *c, const double *ref, double *Phi, double *Phi_inv)
+{
+    phi_matrices(c, ref, Phi, Phi_inv);
+}

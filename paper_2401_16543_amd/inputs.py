@@ -1,0 +1,212 @@
+"""Seeded synthetic initial states for the KFVM-WENO right-hand side.
+
+This module holds no part of the method's arithmetic: it only draws random
+fields and averages them over cells.  Both the GPU path and the CPU oracle are
+fed from it; it imports neither.
+
+Domain: the periodic unit box [0, 1)^d with n cells per axis.  Primitive fields
+(rho, u_1..u_d, p) are evaluated at quadrature points and converted to the
+conserved variables (rho, rho u, E = p/(gamma-1) + rho |u|^2 / 2) before
+averaging, so cell averages are those of the conserved variables.
+
+* smooth(seed, d, M): every primitive variable gets its own M Fourier modes with
+  integer wavevectors k in [-4, 4]^d \\ {0}, amplitudes a ~ U(0,1) normalised to
+  sum 1 and phases ~ U(0, 2 pi):
+      rho = 1 + 0.2 S_rho,  u_i = 0.5 S_ui,  p = 1 + 0.2 S_p,
+  with S = sum_m a_m sin(2 pi k_m . x + phi_m).
+* discontinuous(seed, d, n_disc, r_rho_max, r_p_max): the smooth field with its
+  velocity amplitude scaled by s ~ U(0, 1), then n_disc regions applied in turn,
+  each a (periodic) ball with centre ~ U[0,1)^d and radius ~ U(0.05, 0.25) or a
+  periodic slab with a small-integer normal and half-width ~ U(0.05, 0.15); inside
+  a region rho is multiplied by r_rho and p by r_p, each log-uniform on
+  [1, r_max] and inverted with probability 1/2.
+* isentropic_vortex(d): the vortex of the paper's convergence study on
+  [-10, 10]^2 (section 6.1), for validation runs.
+
+Cell averages use a tensor Gauss-Legendre rule (smooth fields) or sub-cell
+midpoints (fields with jumps), evaluated with torch in float64 on any device,
+in slabs along the slowest axis to bound memory.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_SLAB_POINTS = 1 << 24   # quadrature points evaluated per slab
+
+
+@dataclass
+class FieldSpec:
+    d: int
+    modes: list                     # per primitive variable: (k [M, d], a [M], phi [M])
+    base: list
+    amp: list
+    regions: list = field(default_factory=list)   # (kind, params, r_rho, r_p)
+    domain_lo: float = 0.0
+    domain_hi: float = 1.0
+    vortex: bool = False
+
+
+_SLAB_NORMALS_2D = [(1, 0), (0, 1), (1, 1), (1, -1), (1, 2), (2, 1)]
+_SLAB_NORMALS_3D = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1),
+                    (1, -1, 0), (1, 1, 1), (1, 2, 0), (2, 1, 1)]
+
+
+def _draw_modes(rng, d, M):
+    out = []
+    for _ in range(d + 2):
+        ks = []
+        while len(ks) < M:
+            k = rng.integers(-4, 5, size=d)
+            if np.any(k != 0):
+                ks.append(k)
+        a = rng.uniform(0.0, 1.0, size=M)
+        a = a / a.sum()
+        phi = rng.uniform(0.0, 2 * np.pi, size=M)
+        out.append((np.array(ks, dtype=np.float64), a, phi))
+    return out
+
+
+def smooth(seed: int, d: int, M: int) -> FieldSpec:
+    rng = np.random.default_rng(seed)
+    return FieldSpec(d=d, modes=_draw_modes(rng, d, M), base=[1.0] + [0.0] * d + [1.0],
+                     amp=[0.2] + [0.5] * d + [0.2])
+
+
+def discontinuous(seed: int, d: int, n_disc: int, r_rho_max: float, r_p_max: float,
+                  M: int = 8) -> FieldSpec:
+    rng = np.random.default_rng(seed)
+    modes = _draw_modes(rng, d, M)
+    s = rng.uniform(0.0, 1.0)
+    spec = FieldSpec(d=d, modes=modes, base=[1.0] + [0.0] * d + [1.0],
+                     amp=[0.2] + [0.5 * s] * d + [0.2])
+    normals = _SLAB_NORMALS_2D if d == 2 else _SLAB_NORMALS_3D
+    for _ in range(n_disc):
+        r_rho = math.exp(rng.uniform(0.0, math.log(r_rho_max)))
+        r_p = math.exp(rng.uniform(0.0, math.log(r_p_max)))
+        if rng.uniform() < 0.5:
+            r_rho = 1.0 / r_rho
+        if rng.uniform() < 0.5:
+            r_p = 1.0 / r_p
+        if rng.uniform() < 0.5:
+            centre = rng.uniform(0.0, 1.0, size=d)
+            radius = rng.uniform(0.05, 0.25)
+            spec.regions.append(("ball", (centre, radius), r_rho, r_p))
+        else:
+            nrm = np.array(normals[rng.integers(len(normals))], dtype=np.float64)
+            offset = rng.uniform(0.0, 1.0)
+            half = rng.uniform(0.05, 0.15)
+            spec.regions.append(("slab", (nrm, offset, half), r_rho, r_p))
+    return spec
+
+
+def isentropic_vortex(gamma: float = 1.4) -> FieldSpec:
+    return FieldSpec(d=2, modes=[], base=[], amp=[], domain_lo=-10.0, domain_hi=10.0, vortex=True)
+
+
+# ---------------------------------------------------------------------------
+def _primitive(spec: FieldSpec, X: torch.Tensor, gamma: float):
+    """Primitive variables [d + 2, P] at points X [P, d] (domain coordinates)."""
+    d = spec.d
+    if spec.vortex:
+        x, y = X[:, 0], X[:, 1]
+        om = 5.0 * math.sqrt(2.0 * math.e) / (4.0 * math.pi) * torch.exp(-0.5 * (x * x + y * y))
+        base = 1.0 + (1.0 - gamma) / 2.0 * om * om
+        rho = base ** (1.0 / (gamma - 1.0))
+        p = base ** (gamma / (gamma - 1.0)) / gamma
+        return torch.stack([rho, 1.0 - y * om, 1.0 + x * om, p])
+    out = []
+    for j in range(d + 2):
+        k, a, phi = (torch.as_tensor(t, dtype=torch.float64, device=X.device) for t in spec.modes[j])
+        arg = 2.0 * math.pi * (X @ k.T) + phi            # [P, M]
+        out.append(spec.base[j] + spec.amp[j] * (torch.sin(arg) @ a))
+    V = torch.stack(out)
+    for kind, prm, r_rho, r_p in spec.regions:
+        if kind == "ball":
+            centre, radius = prm
+            c = torch.as_tensor(centre, dtype=torch.float64, device=X.device)
+            dd = X - c
+            dd = dd - torch.round(dd)                    # periodic minimal image
+            inside = (dd * dd).sum(1) < radius * radius
+        else:
+            nrm, offset, half = prm
+            nv = torch.as_tensor(nrm, dtype=torch.float64, device=X.device)
+            s = X @ nv - offset
+            s = s - torch.round(s)
+            inside = s.abs() < half
+        V[0] = torch.where(inside, V[0] * r_rho, V[0])
+        V[d + 1] = torch.where(inside, V[d + 1] * r_p, V[d + 1])
+    return V
+
+
+def _conserved(V: torch.Tensor, d: int, gamma: float):
+    rho, u, p = V[0], V[1:d + 1], V[d + 1]
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u).sum(0)
+    return torch.cat([rho[None], rho[None] * u, E[None]])
+
+
+def _rule(kind: str, q: int):
+    if kind == "gauss":
+        x, w = np.polynomial.legendre.leggauss(q)
+        return 0.5 * x, 0.5 * w                          # on [-1/2, 1/2], weights sum to 1
+    x = (np.arange(q) + 0.5) / q - 0.5
+    return x, np.full(q, 1.0 / q)
+
+
+def cell_averages(spec: FieldSpec, n: int, gamma: float, *, rule: str = "gauss", q: int = 3,
+                  device="cpu") -> torch.Tensor:
+    """Conserved cell averages, float64 tensor [d + 2, (n,)*d] on `device`."""
+    d = spec.d
+    h = (spec.domain_hi - spec.domain_lo) / n
+    xq, wq = _rule(rule, q)
+    xq = torch.as_tensor(xq, dtype=torch.float64, device=device)
+    wq = torch.as_tensor(wq, dtype=torch.float64, device=device)
+    # tensor rule offsets [Q^d, d] and weights [Q^d]
+    grids = torch.meshgrid(*([xq] * d), indexing="ij")
+    off = torch.stack([g.reshape(-1) for g in grids], 1) * h
+    wg = torch.meshgrid(*([wq] * d), indexing="ij")
+    wts = torch.ones_like(wg[0]).reshape(-1)
+    for g in wg:
+        wts = wts * g.reshape(-1)
+    out = torch.empty((d + 2,) + (n,) * d, dtype=torch.float64, device=device)
+    idx = torch.arange(n, dtype=torch.float64, device=device)
+    centres_1d = spec.domain_lo + (idx + 0.5) * h
+    per_slab = max(1, _SLAB_POINTS // (off.shape[0] * n ** (d - 1)))
+    for s0 in range(0, n, per_slab):
+        s1 = min(n, s0 + per_slab)
+        # numpy layout (z, y, x) for 3D, (y, x) for 2D; coordinates (x, y[, z])
+        axes = [centres_1d[s0:s1]] + [centres_1d] * (d - 1)
+        mesh = torch.meshgrid(*axes, indexing="ij")      # slowest axis first
+        C = torch.stack([m.reshape(-1) for m in reversed(mesh)], 1)   # [cells, d] as (x, y[, z])
+        X = (C[:, None, :] + off[None, :, :]).reshape(-1, d)
+        U = _conserved(_primitive(spec, X, gamma), d, gamma)          # [nv, cells * Q^d]
+        U = (U.reshape(d + 2, C.shape[0], -1) * wts).sum(-1)
+        out[:, s0:s1] = U.reshape((d + 2, s1 - s0) + (n,) * (d - 1))
+    return out
+
+
+def config_state(name: str, device="cpu", n: int | None = None) -> tuple[torch.Tensor, dict]:
+    """Initial state of a named workload, optionally at another resolution n."""
+    cfg = WORKLOADS[name]
+    nn = n or cfg["n"]
+    spec = cfg["spec"]()
+    rule, q = ("gauss", cfg["R"] + 1) if not spec.regions else ("midpoint", 4 if cfg["d"] == 2 else 2)
+    U = cell_averages(spec, nn, cfg["gamma"], rule=rule, q=q, device=device)
+    return U, dict(cfg, n=nn)
+
+
+WORKLOADS = {
+    "2d_smooth_64": dict(d=2, n=64, R=2, gamma=1.4, cfl=0.4, steps=10,
+                         spec=lambda: smooth(1, 2, 8)),
+    "2d_jumps_1024": dict(d=2, n=1024, R=2, gamma=1.4, cfl=0.4, steps=200,
+                          spec=lambda: discontinuous(2, 2, 6, 10.0, 100.0)),
+    "3d_smooth_256": dict(d=3, n=256, R=2, gamma=5.0 / 3.0, cfl=0.4, steps=50,
+                          spec=lambda: smooth(3, 3, 16)),
+    "2d_jumps_2048": dict(d=2, n=2048, R=2, gamma=1.4, cfl=0.4, steps=100,
+                          spec=lambda: discontinuous(4, 2, 6, 10.0, 100.0)),
+    "3d_jumps_384_r3": dict(d=3, n=384, R=3, gamma=1.4, cfl=0.4, steps=30,
+                            spec=lambda: discontinuous(5, 3, 4, 10.0, 50.0, M=16)),
+}
