@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the KFVM-WENO right-hand side on one MI355X.
+
+A step is one SSP-RK3 step (three right-hand-side evaluations, each the
+reconstruction, face-flux and update kernels) over the whole grid of the
+workload, with the state already resident in HBM.  The metric is cell-updates
+per second per Runge-Kutta stage: cells * 3 * steps / elapsed.
+
+Prints one JSON line.  `roofline` covers the dominant kernel (reconstruction):
+its algorithmic FP64 flops per launch over its average launch time, measured
+with HIP events on the library's stream over the timed steps.  `cpu_baseline`
+times the FP64 CPU oracle on a bounded periodic sub-box of the same initial
+state (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "cell-updates/sec per RK stage, plain FP64 vs mixed+learned at stated L1 error"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+HBM_PEAK_GBS = 8000.0
+
+# (sum of N_q over the stencils, face points, derivative rows, stencils, |S0|)
+_SHAPES = {(2, 2): (38, 8, 5, 6, 13), (2, 3): (82, 12, 9, 6, 29),
+           (3, 2): (106, 24, 9, 8, 33), (3, 3): (348, 54, 19, 8, 123)}
+
+
+def recon_flops_per_cell(d: int, R: int) -> int:
+    """Algorithmic FP64 flops of the reconstruction kernel per cell (FMA = 2):
+    per variable the dot products of every stencil row with its gathered values,
+    the squared-derivative sums, the nonlinear weights and the WENO-AO blend;
+    plus the linearised-primitive transform of the S0 values."""
+    sn, npts, nder, nst, n0 = _SHAPES[(d, R)]
+    nv = d + 2
+    per_var = 2 * (npts + nder) * sn + 2 * nder * nst + 5 * nst + 2 * npts * nst
+    return nv * per_var + n0 * (5 * d + 3)
+
+
+def recon_bytes_per_cell(d: int, R: int) -> int:
+    """Algorithmic HBM bytes of the reconstruction kernel per cell: the cell's
+    conserved average read once, its face-point values and two limiter factors written."""
+    _, npts, _, _, _ = _SHAPES[(d, R)]
+    nv = d + 2
+    return 8 * (nv + npts * nv + 2)
+
+
+def cpu_baseline(U_host, cfg, budget_s: float):
+    """Time the oracle's whole-grid RHS on a periodic sub-box of the same state."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import core
+    d, R, gamma = cfg["d"], cfg["R"], cfg["gamma"]
+    core.build()
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+
+    def run(m):
+        sl = (slice(None),) + (slice(0, m),) * d
+        Us = U_host[sl].copy()
+        o = core.Oracle(d, R, (m,) * d, dx=[1.0 / cfg["n"]] * d, gamma=gamma)
+        t = time.perf_counter()
+        o.rhs(Us)
+        return time.perf_counter() - t
+
+    m = 16 if d == 3 else 64
+    t = run(m)
+    # grow the box until one RHS takes about a third of the budget
+    while t < budget_s / 3 and m < cfg["n"]:
+        grow = min(2.0, max(1.2, (budget_s / 3 / max(t, 1e-3)) ** (1.0 / d)))
+        m = min(cfg["n"], int(m * grow))
+        t = run(m)
+    cells = m ** d
+    return {"value": cells / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole-grid RHS (one RK stage) of the FP64 oracle on the periodic "
+                      f"{'x'.join([str(m)] * d)} corner sub-box of the {cfg['n']}^{d} initial state, "
+                      f"{t:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d_smooth_256")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              f"(the path would shard by spatial domain; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_16543_amd import inputs, kfvm
+
+    U, cfg = inputs.config_state(args.workload, device="cuda")
+    d, n, R, gamma = cfg["d"], cfg["n"], cfg["R"], cfg["gamma"]
+    ncell = n ** d
+    print(f"# workload {args.workload}: {n}^{d} cells, R={R}, gamma={gamma:.4f}", file=sys.stderr, flush=True)
+    dev = kfvm.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
+    dt = dev.cfl_dt(U, cfg["cfl"])
+    for _ in range(args.warmup):
+        dev.step(U, dt)
+    torch.cuda.synchronize()
+    if dev.status() != kfvm.KFVM_OK:
+        raise SystemExit("non-physical state during warm-up")
+
+    dev.set_timing(True)
+    dev.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dev.step(U, dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = dev.kernel_times()
+    dev.set_timing(False)
+    if dev.status() != kfvm.KFVM_OK:
+        raise SystemExit("non-physical state during the timed steps")
+
+    stages = 3 * args.steps
+    value = ncell * stages / elapsed
+    rec_ms, rec_n = kt["recon"]
+    rec_avg_s = rec_ms / rec_n / 1e3
+    flops = recon_flops_per_cell(d, R) * ncell
+    achieved = flops / rec_avg_s / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [n] * d, "R": R, "order": 2 * R + 1,
+                   "gamma": gamma, "cfl": cfg["cfl"], "path": "plain_fp64", "riemann": "hllc",
+                   "limiter": "on, kappa=0.5"},
+        "roofline": {"kernel": "k_recon", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_cell": recon_flops_per_cell(d, R),
+                     "alg_bytes_per_cell": recon_bytes_per_cell(d, R),
+                     "hbm_gbs_alg": recon_bytes_per_cell(d, R) * ncell / rec_avg_s / 1e9,
+                     "avg_launch_ms": rec_avg_s * 1e3},
+        "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(U.cpu().numpy(), cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * kfvm.h - C-ABI of the MI355X (gfx950) KFVM-WENO right-hand-side library.
+ *
+ * The library evaluates the semi-discrete right-hand side of the compressible
+ * Euler equations (paper section 1, eq. model and eq. euler, ideal-gas law with
+ * ratio of specific heats gamma) on a periodic uniform Cartesian grid with the
+ * kernel-based finite volume WENO-AO scheme of May & Lee (arXiv 2401.16543),
+ * and advances it with the three-stage SSP Runge-Kutta method of Shu & Osher.
+ *
+ * The right-hand side follows the paper's section 5.3: per cell the linearised
+ * primitive variables W = Phi U with Phi from the cell's own average (section
+ * 3.4.2, eq. consToLPMat), point values and derivatives from precomputed kernel
+ * reconstruction vectors (section 2.1, eq. reconVec; section 3.3), smoothness
+ * indicators (eq. smoothIndic), WENO-JS form nonlinear weights with eps = 1e-40
+ * (eq. nlinWts), the WENO-AO blend (eq. wenoAOrec), u = Phi^-1 w (eq.
+ * recVarToCons), the positivity limiter of section 4, an HLLC or HLL Riemann
+ * solver with Batten wavespeeds at every face Gauss point (section 6), and the
+ * Gauss-Legendre face integral of the fluxes.
+ *
+ * Conventions
+ *  - Every entry point returns int: KFVM_OK (0) or a negative error code; no
+ *    C++ exception crosses the ABI.  kfvm_last_error() gives a message.
+ *  - State arrays are device pointers to float64 in struct-of-arrays layout
+ *    U[v][z][y][x] (x fastest), v over (rho, rho u, rho v[, rho w], E): 4
+ *    variables in 2D, 5 in 3D.  They are owned by the caller.
+ *  - Work is queued on the context's HIP stream (kfvm_set_stream; default the
+ *    null stream) and is asynchronous unless stated otherwise.
+ *  - A context owns its weight tables and workspace, allocated in kfvm_init
+ *    and freed in kfvm_destroy.  Contexts are independent; one context must not
+ *    be used from two threads at once.
+ */
+#ifndef KFVM_H
+#define KFVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KFVM_OK = 0,
+    KFVM_ERR_ARG = -1,          /* bad dimension, order, size, pointer or mode */
+    KFVM_ERR_HIP = -2,          /* HIP runtime error; message in kfvm_last_error */
+    KFVM_ERR_NONPHYSICAL = -3,  /* a cell average with rho <= 0, p <= 0 or a non-finite value */
+    KFVM_ERR_STATE = -4         /* context not initialised, or a required setting missing */
+};
+
+enum { KFVM_FP64 = 0, KFVM_SPLIT_F16 = 1, KFVM_SPLIT_BF16 = 2 };   /* kfvm_set_precision */
+enum { KFVM_HLLC = 0, KFVM_HLL = 1 };                              /* kfvm_set_riemann */
+
+typedef struct kfvm_ctx kfvm_ctx;
+
+/* Periodic box of n[a] cells of width dx[a] per axis a (n[2], dx[2] ignored in 2D).
+ * Every n[a] must be at least 2R + 2. */
+typedef struct {
+    int dim;
+    int n[3];
+    double dx[3];
+} kfvm_mesh;
+
+/* Reconstruction vectors (section 2.1, eq. recVec1; section 3.3; section 5.1),
+ * in unit-cell coordinates.  Layout, which must match the library's own stencil
+ * definition exactly (it is validated):
+ *  - offsets[n0][dim]: S0 = {|i|^2 <= R^2} in lexicographic order of (x, y[, z]),
+ *    x slowest (section 3.1);
+ *  - stencil q = 0 is S0, q = 1 the ball of radius R-1, q >= 2 the biased cones
+ *    along +x, -x, +y, -y[, +z, -z]; members[stencil_ptr[q] .. stencil_ptr[q+1])
+ *    are indices into S0 in increasing order;
+ *  - tables: for each stencil in turn a row-major [n_pts + n_der][N_q] block:
+ *    n_pts face-point rows, s = (2 a + side) R^(dim-1) + g (normal axis a, side 0
+ *    the lower face, g the Gauss index over the transverse axes, first slowest),
+ *    then n_der rows for the derivatives 0 < |alpha| <= R ordered by degree, then
+ *    lexicographically descending;
+ *  - gamma_lin[n_stencils]: linear weights (section 3.2).
+ * The library copies what it needs; the caller keeps ownership. */
+typedef struct {
+    int dim, R;
+    int n0;
+    const int *offsets;
+    int n_stencils;
+    const int *stencil_ptr;
+    const int *members;
+    int n_pts, n_der;
+    const double *tables;
+    const double *gamma_lin;
+} kfvm_weights;
+
+/* Host-side statistics, filled by kfvm_stats (synchronising). */
+typedef struct {
+    long long limiter_cells;     /* cells whose Riemann states the limiter scaled, last RHS */
+    long long weno_cell_vars;    /* (cell, variable) pairs reconstructed with WENO-AO, last RHS */
+    long long cell_vars;         /* all (cell, variable) pairs */
+    int error;                   /* sticky device error code (0 or KFVM_ERR_NONPHYSICAL) */
+} kfvm_stats_t;
+
+/* Create a context for `mesh`.  order 5 selects R = 2, order 7 selects R = 3
+ * (the full stencil reproduces polynomials of degree 2R-1, section 3.1).
+ * gamma > 1 is the ratio of specific heats.  weights == NULL builds the tables
+ * in binary128 arithmetic (kfvm_weights_build); otherwise they are validated
+ * and copied.  Allocates the device workspace and uploads the tables on the
+ * current HIP device.  Defaults: FP64, HLLC, limiter on with kappa = 0.5. */
+int kfvm_init(kfvm_ctx **ctx, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights);
+
+/* dUdt = L(U): the right-hand side on the whole grid.  U and dUdt are distinct
+ * device buffers of nvar * ncells float64 (aliasing is rejected). */
+int kfvm_rhs(kfvm_ctx *ctx, const double *U, double *dUdt);
+
+/* One SSP-RK3 step of size dt on U, in place:
+ *   U1 = U + dt L(U),  U2 = 3/4 U + 1/4 (U1 + dt L(U1)),  U <- 1/3 U + 2/3 (U2 + dt L(U2)).
+ * If a non-physical state is met, the contents of U are unspecified and the
+ * error is reported by kfvm_status / kfvm_stats (or returned, see
+ * kfvm_set_checking). */
+int kfvm_step(kfvm_ctx *ctx, double *U, double dt);
+
+/* dt = cfl / max_cells sum_a (|u_a| + c_s) / dx_a.  Synchronising; the result is
+ * written to host memory. */
+int kfvm_cfl_dt(kfvm_ctx *ctx, const double *U, double cfl, double *dt_host);
+
+/* Queue subsequent work on this HIP stream (hipStream_t passed as void*). */
+int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
+
+/* Arithmetic of the weight-apply and smoothness-indicator contractions:
+ * KFVM_FP64 (default), or split hi/lo half-precision operands on the matrix
+ * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
+ * nonlinear-weight normalisation, the limiter, the Riemann solver and the
+ * Runge-Kutta update stay in float64. */
+int kfvm_set_precision(kfvm_ctx *ctx, int mode);
+
+/* Positivity limiter of section 4 with flattener eta = 0: enabled != 0 turns it
+ * on; bounds are widened by the factor (1 +- kappa), 0 <= kappa < 1. */
+int kfvm_set_limiter(kfvm_ctx *ctx, int enabled, double kappa);
+
+/* KFVM_HLLC (default) or KFVM_HLL (section 6). */
+int kfvm_set_riemann(kfvm_ctx *ctx, int solver);
+
+/* checking != 0: kfvm_rhs and kfvm_step synchronise the stream and return
+ * KFVM_ERR_NONPHYSICAL if the device raised it (the flag is then cleared). */
+int kfvm_set_checking(kfvm_ctx *ctx, int checking);
+
+/* Synchronise; return and clear the sticky device error code. */
+int kfvm_status(kfvm_ctx *ctx);
+
+/* Synchronise and fill *out. */
+int kfvm_stats(kfvm_ctx *ctx, kfvm_stats_t *out);
+
+/* Test hook: the limited Riemann states of the last kfvm_rhs input, converted to
+ * conserved variables, as states[cell][s][v] (device buffer of ncells * n_pts *
+ * nvar float64).  Recomputes them from U. */
+int kfvm_face_states(kfvm_ctx *ctx, const double *U, double *states);
+
+/* Build the reconstruction tables of (dim, R) with kernel length scale ell_hat
+ * (in cells; the paper uses 5) into tables[capacity], layout as in kfvm_weights.
+ * Returns the number of float64 written, or a negative code. Host only. */
+int kfvm_weights_build(int dim, int R, double ell_hat, double *tables, int capacity);
+
+/* Number of float64 in the tables of (dim, R), or a negative code. */
+int kfvm_weights_size(int dim, int R);
+
+/* on != 0: bracket every subsequent kernel launch with HIP events on the
+ * context's stream (adds a few microseconds per launch). */
+int kfvm_set_timing(kfvm_ctx *ctx, int on);
+
+/* Synchronise; write the summed device time in milliseconds and the launch
+ * count of each kernel class since the last call (index 0: reconstruction,
+ * 1: face flux, 2: flux difference and stage update) into ms[n], launches[n]
+ * (n >= 3), and forget the recorded events. */
+int kfvm_kernel_times(kfvm_ctx *ctx, double *ms, long long *launches, int n);
+
+/* Message of the last error on this context (never NULL). */
+const char *kfvm_last_error(const kfvm_ctx *ctx);
+
+/* Free the context and its device memory (after synchronising its stream). */
+void kfvm_destroy(kfvm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFVM_H */

@@ -1,0 +1,356 @@
+// C-ABI of the KFVM-WENO library: context life cycle, argument checking,
+// workspace ownership and dispatch to the HIP kernels.  See include/kfvm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/kfvm.h"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+struct kfvm_ctx {
+    int dim = 0, R = 0, nvar = 0;
+    kfvm::Geom geom{};
+    kfvm::Limiter lim{1, 0.5};
+    int riemann = KFVM_HLLC;
+    int precision = KFVM_FP64;
+    int checking = 0;
+    hipStream_t stream = nullptr;
+    double *d_tables = nullptr;
+    kfvm::Work work{};
+    double *d_dt = nullptr;
+    std::vector<void *> allocs;
+    std::string msg;
+    // per-kernel timing (kfvm_set_timing): event pairs per launch, summed on query
+    int timing = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+    hipEvent_t pending[kfvm::KT_COUNT] = {};
+};
+
+namespace {
+
+thread_local std::string g_init_msg;
+
+int fail(kfvm_ctx *c, int code, const std::string &m)
+{
+    if (c) c->msg = m; else g_init_msg = m;
+    return code;
+}
+
+int hip_fail(kfvm_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, KFVM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                           \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);     \
+    } while (0)
+
+template <int D, int R>
+bool layout_matches(const kfvm_weights *w)
+{
+    constexpr kfvm::Stencil<D, R> st{};
+    using S = kfvm::Stencil<D, R>;
+    if (w->dim != D || w->R != R || w->n0 != S::N0 || w->n_stencils != S::NST) return false;
+    if (w->n_pts != S::NPTS || w->n_der != S::NDER) return false;
+    if (!w->offsets || !w->stencil_ptr || !w->members || !w->tables) return false;
+    for (int h = 0; h < S::N0; ++h)
+        for (int a = 0; a < D; ++a)
+            if (w->offsets[h * D + a] != st.off[h][a]) return false;
+    if (w->stencil_ptr[0] != 0) return false;
+    for (int q = 0; q < S::NST; ++q) {
+        if (w->stencil_ptr[q + 1] - w->stencil_ptr[q] != st.nmem[q]) return false;
+        for (int j = 0; j < st.nmem[q]; ++j)
+            if (w->members[w->stencil_ptr[q] + j] != st.mem[q][j]) return false;
+    }
+    return true;
+}
+
+bool layout_matches(int dim, int R, const kfvm_weights *w)
+{
+    if (dim == 2 && R == 2) return layout_matches<2, 2>(w);
+    if (dim == 2 && R == 3) return layout_matches<2, 3>(w);
+    if (dim == 3 && R == 2) return layout_matches<3, 2>(w);
+    if (dim == 3 && R == 3) return layout_matches<3, 3>(w);
+    return false;
+}
+
+int npts_of(int dim, int R)
+{
+    if (dim == 2 && R == 2) return kfvm::Stencil<2, 2>::NPTS;
+    if (dim == 2 && R == 3) return kfvm::Stencil<2, 3>::NPTS;
+    if (dim == 3 && R == 2) return kfvm::Stencil<3, 2>::NPTS;
+    return kfvm::Stencil<3, 3>::NPTS;
+}
+
+int alloc(kfvm_ctx *c, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    c->allocs.push_back(*p);
+    return KFVM_OK;
+}
+
+int sync_check(kfvm_ctx *c)
+{
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int err = 0;
+    HIP_TRY(c, hipMemcpy(&err, c->work.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err != 0) {
+        int zero = 0;
+        HIP_TRY(c, hipMemcpy(c->work.err, &zero, sizeof(int), hipMemcpyHostToDevice));
+        return fail(c, err, "non-physical state (rho <= 0, p <= 0 or non-finite) met on the device");
+    }
+    return KFVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights)
+{
+    if (!out || !mesh) return fail(nullptr, KFVM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (mesh->dim != 2 && mesh->dim != 3) return fail(nullptr, KFVM_ERR_ARG, "dim must be 2 or 3");
+    if (order != 5 && order != 7) return fail(nullptr, KFVM_ERR_ARG, "order must be 5 (R = 2) or 7 (R = 3)");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(nullptr, KFVM_ERR_ARG, "gamma must exceed 1");
+    const int dim = mesh->dim, R = order == 5 ? 2 : 3;
+    long ncell = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (mesh->n[a] < 2 * R + 2) return fail(nullptr, KFVM_ERR_ARG, "every n must be at least 2R + 2");
+        if (!(mesh->dx[a] > 0.0) || !std::isfinite(mesh->dx[a])) return fail(nullptr, KFVM_ERR_ARG, "bad dx");
+        ncell *= mesh->n[a];
+    }
+    if (ncell > (1L << 31)) return fail(nullptr, KFVM_ERR_ARG, "grid too large");
+
+    kfvm_ctx *c = new kfvm_ctx();
+    c->dim = dim;
+    c->R = R;
+    c->nvar = dim + 2;
+    for (int a = 0; a < 3; ++a) {
+        c->geom.n[a] = a < dim ? mesh->n[a] : 1;
+        c->geom.dx[a] = a < dim ? mesh->dx[a] : 1.0;
+    }
+    c->geom.ncell = ncell;
+    c->geom.gamma = gamma;
+
+    const int ntab = kfvm_weights_size(dim, R);
+    std::vector<double> host(ntab);
+    if (weights) {
+        if (!layout_matches(dim, R, weights)) {
+            delete c;
+            return fail(nullptr, KFVM_ERR_ARG, "weights layout does not match the library's stencils");
+        }
+        std::memcpy(host.data(), weights->tables, sizeof(double) * ntab);
+    } else {
+        if (kfvm_weights_build(dim, R, 5.0, host.data(), ntab) != ntab) {
+            delete c;
+            return fail(nullptr, KFVM_ERR_STATE, "weight build failed");
+        }
+    }
+
+    const int nv = c->nvar, npts = npts_of(dim, R);
+    int rc = KFVM_OK;
+    auto A = [&](void **p, size_t bytes) { if (rc == KFVM_OK) rc = alloc(c, p, bytes); };
+    A((void **)&c->d_tables, sizeof(double) * ntab);
+    A((void **)&c->work.face, sizeof(double) * (size_t)npts * nv * ncell);
+    A((void **)&c->work.theta, sizeof(double) * 2 * (size_t)ncell);
+    A((void **)&c->work.fbar, sizeof(double) * (size_t)dim * nv * ncell);
+    A((void **)&c->work.stage[0], sizeof(double) * (size_t)nv * ncell);
+    A((void **)&c->work.stage[1], sizeof(double) * (size_t)nv * ncell);
+    A((void **)&c->work.cfl_part, sizeof(double) * 1024);
+    A((void **)&c->work.err, sizeof(int) * 4);
+    A((void **)&c->work.counts, sizeof(uint32_t) * 4);
+    A((void **)&c->d_dt, sizeof(double));
+    if (rc != KFVM_OK) {
+        g_init_msg = c->msg;
+        kfvm_destroy(c);
+        return rc;
+    }
+    hipError_t e = hipMemcpy(c->d_tables, host.data(), sizeof(double) * ntab, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->work.err, 0, sizeof(int) * 4);
+    if (e != hipSuccess) {
+        hip_fail(nullptr, e, "upload");
+        kfvm_destroy(c);
+        return KFVM_ERR_HIP;
+    }
+    *out = c;
+    return KFVM_OK;
+}
+
+static void record_event(void *self, int kind, hipStream_t s, int begin)
+{
+    kfvm_ctx *c = (kfvm_ctx *)self;
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return;
+    hipEventRecord(ev, s);
+    if (begin) {
+        c->pending[kind] = ev;
+    } else {
+        c->events.push_back({kind, {c->pending[kind], ev}});
+        c->pending[kind] = nullptr;
+    }
+}
+
+static kfvm::Timing timing_of(kfvm_ctx *c) { return kfvm::Timing{c->timing, record_event, c}; }
+
+static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
+{
+    kfvm::Tables t{c->d_tables};
+    hipError_t e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage,
+                                         dt, c->stream, timing_of(c));
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    return KFVM_OK;
+}
+
+int kfvm_rhs(kfvm_ctx *c, const double *U, double *dUdt)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !dUdt) return fail(c, KFVM_ERR_ARG, "null buffer");
+    if (U == dUdt) return fail(c, KFVM_ERR_ARG, "U and dUdt must not alias");
+    int rc = stage_call(c, U, U, dUdt, 0, 0.0);
+    if (rc == KFVM_OK && c->checking) rc = sync_check(c);
+    return rc;
+}
+
+int kfvm_step(kfvm_ctx *c, double *U, double dt)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U) return fail(c, KFVM_ERR_ARG, "null buffer");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, KFVM_ERR_ARG, "dt must be positive and finite");
+    double *U1 = c->work.stage[0], *U2 = c->work.stage[1];
+    int rc = stage_call(c, U, U, U1, 1, dt);
+    if (rc == KFVM_OK) rc = stage_call(c, U, U1, U2, 2, dt);
+    if (rc == KFVM_OK) rc = stage_call(c, U, U2, U, 3, dt);
+    if (rc == KFVM_OK && c->checking) rc = sync_check(c);
+    return rc;
+}
+
+int kfvm_cfl_dt(kfvm_ctx *c, const double *U, double cfl, double *dt_host)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !dt_host) return fail(c, KFVM_ERR_ARG, "null pointer");
+    if (!(cfl > 0.0)) return fail(c, KFVM_ERR_ARG, "cfl must be positive");
+    hipError_t e = kfvm::launch_cfl(c->dim, c->geom, c->work, U, cfl, c->d_dt, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    HIP_TRY(c, hipMemcpyAsync(dt_host, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return sync_check(c);
+}
+
+int kfvm_set_stream(kfvm_ctx *c, void *s)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    c->stream = (hipStream_t)s;
+    return KFVM_OK;
+}
+
+int kfvm_set_precision(kfvm_ctx *c, int mode)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (mode != KFVM_FP64) return fail(c, KFVM_ERR_ARG, "precision mode not available in this build");
+    c->precision = mode;
+    return KFVM_OK;
+}
+
+int kfvm_set_limiter(kfvm_ctx *c, int enabled, double kappa)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!(kappa >= 0.0 && kappa < 1.0)) return fail(c, KFVM_ERR_ARG, "kappa must lie in [0, 1)");
+    c->lim.on = enabled != 0;
+    c->lim.kappa = kappa;
+    return KFVM_OK;
+}
+
+int kfvm_set_riemann(kfvm_ctx *c, int solver)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (solver != KFVM_HLLC && solver != KFVM_HLL) return fail(c, KFVM_ERR_ARG, "unknown Riemann solver");
+    c->riemann = solver;
+    return KFVM_OK;
+}
+
+int kfvm_set_checking(kfvm_ctx *c, int checking)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    c->checking = checking != 0;
+    return KFVM_OK;
+}
+
+int kfvm_status(kfvm_ctx *c)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    return sync_check(c);
+}
+
+int kfvm_stats(kfvm_ctx *c, kfvm_stats_t *out)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!out) return fail(c, KFVM_ERR_ARG, "null pointer");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int err = 0;
+    HIP_TRY(c, hipMemcpy(&err, c->work.err, sizeof(int), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->cell_vars = (long long)c->geom.ncell * c->nvar;
+    out->weno_cell_vars = out->cell_vars;
+    out->error = err;
+    return KFVM_OK;
+}
+
+int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !states) return fail(c, KFVM_ERR_ARG, "null buffer");
+    kfvm::Tables t{c->d_tables};
+    hipError_t e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    return c->checking ? sync_check(c) : KFVM_OK;
+}
+
+int kfvm_set_timing(kfvm_ctx *c, int on)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    c->timing = on != 0;
+    return KFVM_OK;
+}
+
+int kfvm_kernel_times(kfvm_ctx *c, double *ms, long long *launches, int n)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!ms || !launches || n < kfvm::KT_COUNT) return fail(c, KFVM_ERR_ARG, "need room for every kernel class");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    for (auto &e : c->events) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e.second.first, e.second.second) == hipSuccess) {
+            ms[e.first] += t;
+            launches[e.first] += 1;
+        }
+        hipEventDestroy(e.second.first);
+        hipEventDestroy(e.second.second);
+    }
+    c->events.clear();
+    return KFVM_OK;
+}
+
+const char *kfvm_last_error(const kfvm_ctx *c)
+{
+    return c ? c->msg.c_str() : g_init_msg.c_str();
+}
+
+void kfvm_destroy(kfvm_ctx *c)
+{
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    for (auto &e : c->events) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
+    for (void *p : c->allocs) hipFree(p);
+    delete c;
+}
+
+}  // extern "C"

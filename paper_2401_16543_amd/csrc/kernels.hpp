@@ -1,0 +1,56 @@
+// Internal interface between the C-ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kfvm {
+
+struct Geom {
+    int n[3];          // cells per axis (n[2] = 1 in 2D)
+    long ncell;
+    double dx[3];
+    double gamma;
+};
+
+struct Limiter {
+    int on;
+    double kappa;
+};
+
+// Device buffers owned by a context.
+struct Work {
+    double *face;      // [n_pts][nvar][ncell] Riemann states in reconstruction variables
+    double *theta;     // [2][ncell] density and pressure scaling of the limiter
+    double *fbar;      // [dim][nvar][ncell] Gauss-integrated flux through each cell's lower faces
+    double *stage[2];  // [nvar][ncell] Runge-Kutta stage states
+    double *cfl_part;  // per-block maxima of the CFL reduction
+    int *err;          // sticky device error code
+    uint32_t *counts;  // [2] limiter cells, WENO (cell, var) pairs
+    const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
+};
+
+struct Tables {
+    const double *w;   // packed reconstruction tables (device)
+};
+
+// Optional per-kernel timing: when `on`, every launch is bracketed by HIP events
+// on the launch stream; the host sums the elapsed times later.
+enum { KT_RECON = 0, KT_FLUX = 1, KT_UPDATE = 2, KT_COUNT = 3 };
+struct Timing {
+    int on;
+    void (*record)(void *self, int kind, hipStream_t s, int begin);
+    void *self;
+};
+
+// Launchers, one per (dim, R); all asynchronous on `s`.
+// stage: 0 -> out = L(Uin); 1, 2, 3 -> the SSP-RK3 stage combinations with U0.
+hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                           int riemann, const double *U0, const double *Uin, double *out, int stage, double dt,
+                           hipStream_t s, const Timing &tm);
+hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                              const double *U, double *states, hipStream_t s);
+hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
+                      hipStream_t s);
+
+}  // namespace kfvm

@@ -1,0 +1,726 @@
+// FP64 KFVM-WENO right-hand side for gfx950.
+//
+// One Runge-Kutta stage is three kernels:
+//   recon   one thread per cell.  The workgroup stages its tile of conserved
+//           averages plus an R-cell periodic halo in LDS (the ghost fill of
+//           section 5.3 is the index wrap).  Per reconstruction variable the
+//           thread forms W = Phi U over S0 (section 3.4.2) in registers, applies
+//           the derivative rows of every stencil's table (weights are uniform
+//           across the wave: scalar loads, FP64 FMA with an SGPR operand), the
+//           smoothness indicators and WENO-JS weights in FP64 (section 3.3), then
+//           the point rows blended by WENO-AO (eq. wenoAOrec).  The blended
+//           values go to the face buffer in reconstruction variables; the
+//           positivity limiter of section 4 then reads them back (L2-resident)
+//           and stores the cell's two scaling factors.
+//   flux    one thread per cell, Riemann problem at the Gauss points of each
+//           of its lower faces (states rebuilt as U~ + theta (Phi^-1 w - U~)),
+//           HLLC or HLL with Batten wavespeeds, Gauss sum; one flux per face.
+//   update  flux difference divided by the spacing and the SSP-RK3 stage
+//           combination (or the plain right-hand side).
+// All arrays are struct-of-arrays over cells so that every global access is
+// coalesced along x.  Blocks are remapped so that each XCD owns a contiguous
+// run of tiles, which keeps halo re-reads in that XCD's L2.
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+#include <utility>
+
+namespace kfvm {
+namespace {
+
+constexpr double EPS_WENO = 1e-40;
+constexpr int ERR_NONPHYSICAL = -3;
+
+template <int D, int R>
+struct Cfg {
+    using S = Stencil<D, R>;
+    static constexpr S st{};
+    static constexpr int TX = D == 2 ? 16 : 8;
+    static constexpr int TY = D == 2 ? 16 : 8;
+    static constexpr int TZ = D == 2 ? 1 : 4;
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = D == 3 ? TZ + 2 * R : 1;
+    static constexpr int HN = HX * HY * HZ;
+    static constexpr int NV = D + 2;
+};
+
+// linear weights, evaluated as (1 - g_hi) g_lo and (1 - g_hi)(1 - g_lo) / (2 D)
+template <int D>
+__device__ __forceinline__ double lin_w(int q)
+{
+    constexpr double ghi = 0.8, glo = 0.8;
+    return q == 0 ? ghi : (q == 1 ? (1.0 - ghi) * glo : (1.0 - ghi) * (1.0 - glo) / (2 * D));
+}
+
+// Blocks are handed to the 8 XCDs round-robin; give XCD k the k-th contiguous
+// eighth of the tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ long xcd_tile(long bid, long nblk)
+{
+    const long per = (nblk + 7) / 8;
+    const long xcd = bid % 8, local = bid / 8;
+    const long t = xcd * per + local;
+    return t;    // may exceed nblk - 1 for the last XCD: caller checks
+}
+
+// i in [-n, 2n): one wrap (neighbour indices of in-range cells)
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// any i: full periodic reduction (halo of a tile can reach past 2n on small grids)
+__device__ __forceinline__ int wrap_any(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <int D>
+__device__ __forceinline__ double pressure(const double *u, double gam)
+{
+    double ke = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ke += u[1 + a] * u[1 + a];
+    ke = 0.5 * ke / u[0];
+    return (gam - 1.0) * (u[D + 1] - ke);
+}
+
+template <int D>
+__device__ __forceinline__ bool admissible(const double *u, double gam)
+{
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) ok = ok && isfinite(u[v]);
+    return ok && u[0] > 0.0 && pressure<D>(u, gam) > 0.0;
+}
+
+// Phi^-1 w for the reference state (eq. primMat; dE/du_i = rho u_i), dense
+// row order as a matrix-vector product.
+template <int D>
+__device__ __forceinline__ void phi_inv_apply(const double *ref, double gam, const double *w, double *u)
+{
+    constexpr int NV = D + 2, E = D + 1;
+    const double rho = ref[0];
+    double vel[D], uu = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
+    double M[NV][NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) M[i][j] = 0.0;
+    M[0][0] = 1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        M[1 + a][0] = vel[a];
+        M[1 + a][1 + a] = rho;
+        M[E][1 + a] = rho * vel[a];
+    }
+    M[E][0] = uu / 2.0;
+    M[E][E] = 1.0 / (gam - 1.0);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) s += M[i][j] * w[j];
+        u[i] = s;
+    }
+}
+
+// Limited Riemann state: u = Phi^-1 w, then the density and pressure scalings
+// about the cell average, each only when it is active (section 4.2).
+template <int D>
+__device__ __forceinline__ void limited_state(const double *ref, double gam, const double *w, double th_rho,
+                                              double th_p, double *u)
+{
+    constexpr int NV = D + 2;
+    phi_inv_apply<D>(ref, gam, w, u);
+    if (th_rho < 1.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * (u[v] - ref[v]);
+    }
+    if (th_p < 1.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_p * (u[v] - ref[v]);
+    }
+}
+
+// ------------------------------------------------------------------ recon ---
+// Nonzero entries of Phi = dV/dU at the reference state (eq. consToLPMat).
+template <int D>
+struct PhiRows {
+    double inv_rho, m_vel[D], e0, e_mom[D], e_e;
+    __device__ __forceinline__ void init(const double *ref, double gam)
+    {
+        const double rho = ref[0];
+        double vel[D], uu = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
+        inv_rho = 1.0 / rho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            m_vel[a] = -vel[a] / rho;
+            e_mom[a] = (1.0 - gam) * vel[a];
+        }
+        e0 = (gam - 1.0) * uu / 2.0;
+        e_e = gam - 1.0;
+    }
+};
+
+// Component K of W = Phi U at LDS index o, summed in the column order of the
+// dense product (zero entries skipped: adding an exact zero changes nothing).
+template <int D, int K, int HN>
+__device__ __forceinline__ double w_component(const double (*tile)[HN], int o, const PhiRows<D> &ph)
+{
+    if constexpr (K == 0) {
+        return tile[0][o];
+    } else if constexpr (K <= D) {
+        double s = ph.m_vel[K - 1] * tile[0][o];
+        return s + ph.inv_rho * tile[K][o];
+    } else {
+        double s = ph.e0 * tile[0][o];
+#pragma unroll
+        for (int a = 0; a < D; ++a) s += ph.e_mom[a] * tile[1 + a][o];
+        return s + ph.e_e * tile[D + 1][o];
+    }
+}
+
+// Reconstruction of variable K of W at every face point of one cell: smoothness
+// indicators (eq. smoothIndic), nonlinear weights (eq. nlinWts) and the WENO-AO
+// blend (eq. wenoAOrec), or the linear S0 value when the gate says so.
+template <int D, int R, int K>
+__device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
+                                          const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                          double *__restrict__ face, long cell, long ncell)
+{
+    using C = Cfg<D, R>;
+    using S = typename C::S;
+    constexpr int NV = C::NV, N0 = S::N0, NST = S::NST, NPTS = S::NPTS, NDER = S::NDER;
+    double gv[N0];
+    int lcc = lc;
+#pragma unroll
+    for (int h = 0; h < N0; ++h) {
+        const int o = lcc + C::st.off[h][0] + C::HX * (C::st.off[h][1] + C::HY * C::st.off[h][2]);
+        gv[h] = w_component<D, K, C::HN>(tile, o, ph);
+        // Each value is pinned where it is computed and the next group's LDS
+        // index depends on it (empty asm), so at most a group of reads is in
+        // flight: otherwise all N0 x NV reads are issued up front, their
+        // arithmetic is sunk to the first use, and the VGPRs run out.
+        asm volatile("" : "+v"(gv[h]));
+        if (h % 4 == 3) asm volatile("" : "+v"(lcc) : "v"(gv[h]));
+    }
+    const bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    double cq[NST];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) cq[q] = q == 0 ? 1.0 : 0.0;
+    if (use_weno) {
+        double beta[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) beta[q] = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < NDER; ++a) {
+#pragma unroll
+            for (int q = 0; q < NST; ++q) {
+                const double *row = wt + C::st.tab[q] + (NPTS + a) * C::st.nmem[q];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < C::st.nmem[q]; ++j) acc += row[j] * gv[C::st.mem[q][j]];
+                beta[q] += acc * acc;
+            }
+        }
+        double om[NST], sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            om[q] = lin_w<D>(q) / (beta[q] * beta[q] + EPS_WENO);
+            sum += om[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) om[q] /= sum;
+        cq[0] = om[0] / lin_w<D>(0);
+#pragma unroll
+        for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_w<D>(q) / lin_w<D>(0);
+    }
+#pragma unroll 1
+    for (int s = 0; s < NPTS; ++s) {
+        double v[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            v[q] = 0.0;
+            if (q == 0 || use_weno) {
+                const double *row = wt + C::st.tab[q] + s * C::st.nmem[q];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < C::st.nmem[q]; ++j) acc += row[j] * gv[C::st.mem[q][j]];
+                v[q] = acc;
+            }
+        }
+        double f = v[0];
+        if (use_weno) {
+            f = cq[0] * v[0];
+#pragma unroll
+            for (int q = 1; q < NST; ++q) f += cq[q] * v[q];
+        }
+        face[(s * NV + K) * ncell + cell] = f;
+    }
+}
+
+template <int D, int R, int... K>
+__device__ __forceinline__ void recon_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
+                                               const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                               double *__restrict__ face, long cell, long ncell,
+                                               std::integer_sequence<int, K...>)
+{
+    // one pass per variable; the empty asm keeps each pass's LDS reads from
+    // being hoisted into a single register-hungry prologue
+    ((recon_var<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wt, ph, flags, face,
+                         cell, ncell)),
+     ...);
+}
+
+template <int D, int R>
+__global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restrict__ U, const double *__restrict__ wt,
+                                                         double *__restrict__ face, double *__restrict__ theta,
+                                                         int *__restrict__ err, const uint8_t *__restrict__ flags,
+                                                         Geom g, Limiter lim)
+{
+    using C = Cfg<D, R>;
+    using S = typename C::S;
+    constexpr int NV = C::NV, N0 = S::N0, NST = S::NST, NPTS = S::NPTS, NDER = S::NDER;
+    __shared__ double tile[NV][C::HN];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long t = xcd_tile(blockIdx.x, nblk);
+    if (t >= nblk) return;
+    const int bx = (int)(t % nbx), by = (int)((t / nbx) % nby), bz = (int)(t / ((long)nbx * nby));
+    const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+
+    // tile + halo, periodic wrap (the ghost fill)
+    for (int i = threadIdx.x; i < C::HN; i += C::NT) {
+        const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+        const int gx = wrap_any(x0 + hx, g.n[0]), gy = wrap_any(y0 + hy, g.n[1]);
+        const int gz = D == 3 ? wrap_any(z0 + hz, g.n[2]) : 0;
+        const long cell = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[v][i] = U[v * g.ncell + cell];
+    }
+    __syncthreads();
+
+    const int tx = threadIdx.x % C::TX, ty = (threadIdx.x / C::TX) % C::TY, tz = threadIdx.x / (C::TX * C::TY);
+    const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
+    if (cx >= g.n[0] || cy >= g.n[1] || (D == 3 && cz >= g.n[2])) return;
+    const long cell = cx + (long)g.n[0] * (cy + (long)g.n[1] * cz);
+    const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
+
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
+    const double gam = g.gamma;
+    if (!admissible<D>(ref, gam)) {
+        *err = ERR_NONPHYSICAL;
+        theta[cell] = 1.0;
+        theta[g.ncell + cell] = 1.0;
+#pragma unroll 1
+        for (int s = 0; s < NPTS * NV; ++s) face[s * g.ncell + cell] = 0.0;
+        return;
+    }
+
+    // Phi = dV/dU at the cell's own average (eq. consToLPMat): its nonzero
+    // entries, applied row by row with one compile-time pass per variable
+    PhiRows<D> ph;
+    ph.init(ref, gam);
+    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, std::make_integer_sequence<int, NV>{});
+
+    // positivity limiter (section 4) on the cell's Riemann states
+    double th_rho = 1.0, th_p = 1.0;
+    if (lim.on) {
+        double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+        bool ok = true;
+#pragma unroll 1
+        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll 1
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll 1
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int o = lc + dx + C::HX * (dy + C::HY * dz);
+                    double un[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) un[v] = tile[v][o];
+                    ok = ok && admissible<D>(un, gam);
+                    const double pn = pressure<D>(un, gam);
+                    rmax = fmax(rmax, un[0]);
+                    rmin = fmin(rmin, un[0]);
+                    pmin = fmin(pmin, pn);
+                }
+        if (!ok) *err = ERR_NONPHYSICAL;
+        rmax *= 1.0 + lim.kappa;
+        rmin *= 1.0 - lim.kappa;
+        pmin *= 1.0 - lim.kappa;
+        // density scaling (eq. ppThetaRho), only the violated side of each bound
+#pragma unroll 1
+        for (int s = 0; s < NPTS; ++s) {
+            const double rs = face[(s * NV + 0) * g.ncell + cell];   // row 0 of Phi^-1 is e_0
+            if (rs < rmin) th_rho = fmin(th_rho, (ref[0] - rmin) / (ref[0] - rs));
+            else if (rs > rmax) th_rho = fmin(th_rho, (rmax - ref[0]) / (rs - ref[0]));
+        }
+        // pressure scaling (eq. thetapRoot, eq. thetaP): 60 bisection steps
+#pragma unroll 1
+        for (int s = 0; s < NPTS; ++s) {
+            double w[NV], u[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
+            limited_state<D>(ref, gam, w, th_rho, 1.0, u);
+            if (pressure<D>(u, gam) >= pmin) continue;
+            double lo = 0.0, hi = 1.0;
+#pragma unroll 1
+            for (int it = 0; it < 60; ++it) {
+                const double m = 0.5 * (lo + hi);
+                double um[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) um[v] = ref[v] + m * (u[v] - ref[v]);
+                if (pressure<D>(um, gam) >= pmin) lo = m; else hi = m;
+            }
+            th_p = fmin(th_p, lo);
+        }
+    }
+    theta[cell] = th_rho;
+    theta[g.ncell + cell] = th_p;
+}
+
+// ----------------------------------------------------------------- Riemann ---
+template <int D>
+__device__ __forceinline__ void phys_flux(const double *u, int a, double p, double *F)
+{
+    const double un = u[1 + a] / u[0];
+    F[0] = u[1 + a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) F[1 + b] = u[1 + b] * un + (b == a ? p : 0.0);
+    F[D + 1] = un * (u[D + 1] + p);
+}
+
+// HLLC (Toro ch. 10) or HLL, wavespeeds of Batten et al. from Roe averages.
+template <int D, int A>
+__device__ __forceinline__ void riemann(const double *uL, const double *uR, double gam, int hll, double *F)
+{
+    constexpr int NV = D + 2, E = D + 1;
+    const double pL = pressure<D>(uL, gam), pR = pressure<D>(uR, gam);
+    const double rL = uL[0], rR = uR[0];
+    double vL[D], vR[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) { vL[b] = uL[1 + b] / rL; vR[b] = uR[1 + b] / rR; }
+    const double cL = sqrt(gam * pL / rL), cR = sqrt(gam * pR / rR);
+    const double HL = (uL[E] + pL) / rL, HR = (uR[E] + pR) / rR;
+    const double sL = sqrt(rL), sR = sqrt(rR);
+    double qt = 0.0, vtA = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        const double vt = (sL * vL[b] + sR * vR[b]) / (sL + sR);
+        qt += vt * vt;
+        if (b == A) vtA = vt;
+    }
+    const double Ht = (sL * HL + sR * HR) / (sL + sR);
+    const double ct = sqrt((gam - 1.0) * (Ht - 0.5 * qt));
+    const double SL = fmin(vL[A] - cL, vtA - ct);
+    const double SR = fmax(vR[A] + cR, vtA + ct);
+    double FL[NV], FR[NV];
+    phys_flux<D>(uL, A, pL, FL);
+    phys_flux<D>(uR, A, pR, FR);
+    if (SL >= 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FL[v];
+        return;
+    }
+    if (SR <= 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FR[v];
+        return;
+    }
+    if (hll) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) / (SR - SL);
+        return;
+    }
+    const double Ss = (pR - pL + rL * vL[A] * (SL - vL[A]) - rR * vR[A] * (SR - vR[A]))
+                    / (rL * (SL - vL[A]) - rR * (SR - vR[A]));
+    const bool left = Ss >= 0.0;
+    const double SK = left ? SL : SR, rK = left ? rL : rR, pK = left ? pL : pR;
+    double uK[NV], FK[NV], vK[D];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { uK[v] = left ? uL[v] : uR[v]; FK[v] = left ? FL[v] : FR[v]; }
+#pragma unroll
+    for (int b = 0; b < D; ++b) vK[b] = left ? vL[b] : vR[b];
+    const double fac = rK * (SK - vK[A]) / (SK - Ss);
+    double us[NV];
+    us[0] = fac;
+#pragma unroll
+    for (int b = 0; b < D; ++b) us[1 + b] = fac * (b == A ? Ss : vK[b]);
+    us[E] = fac * (uK[E] / rK + (Ss - vK[A]) * (Ss + pK / (rK * (SK - vK[A]))));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FK[v] + SK * (us[v] - uK[v]);
+}
+
+// Gauss weight of transverse index gi: product over the transverse axes,
+// first factor from the fastest-varying index
+template <int D, int R>
+__device__ __forceinline__ double face_weight(int gi)
+{
+    const double w2[2] = {0.5, 0.5};
+    const double w3[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
+    double w = 1.0;
+#pragma unroll
+    for (int t = 0; t < D - 1; ++t) {
+        w *= R == 2 ? w2[gi % R] : w3[gi % R];
+        gi /= R;
+    }
+    return w;
+}
+
+// ------------------------------------------------------------------- flux ---
+template <int D, int R, int A>
+__device__ __forceinline__ void lower_face_flux(const double *__restrict__ U, const double *__restrict__ face,
+                                                const double *__restrict__ theta, const Geom &g, long cell,
+                                                long lower, int hll, double *Fbar)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NG = S::NG;
+    double refL[NV], refR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { refL[v] = U[v * g.ncell + lower]; refR[v] = U[v * g.ncell + cell]; }
+    const double trL = theta[lower], tpL = theta[g.ncell + lower];
+    const double trR = theta[cell], tpR = theta[g.ncell + cell];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
+#pragma unroll 1
+    for (int gi = 0; gi < NG; ++gi) {
+        double wL[NV], wR[NV], uL[NV], uR[NV], F[NV];
+        const int sL = (2 * A + 1) * NG + gi, sR = (2 * A + 0) * NG + gi;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            wL[v] = face[(sL * NV + v) * g.ncell + lower];
+            wR[v] = face[(sR * NV + v) * g.ncell + cell];
+        }
+        limited_state<D>(refL, g.gamma, wL, trL, tpL, uL);
+        limited_state<D>(refR, g.gamma, wR, trR, tpR, uR);
+        riemann<D, A>(uL, uR, g.gamma, hll, F);
+        const double w = face_weight<D, R>(gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[v] += w * F[v];
+    }
+}
+
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_flux(const double *__restrict__ U, const double *__restrict__ face,
+                                              const double *__restrict__ theta, double *__restrict__ fbar,
+                                              int *__restrict__ err, Geom g, int hll)
+{
+    constexpr int NV = D + 2;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
+    const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
+    double F[NV];
+    bool ok = true;
+    {
+        const long lower = wrapi(cx - 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
+        lower_face_flux<D, R, 0>(U, face, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(0 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    {
+        const long lower = cx + (long)g.n[0] * (wrapi(cy - 1, g.n[1]) + (long)g.n[1] * cz);
+        lower_face_flux<D, R, 1>(U, face, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(1 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    if constexpr (D == 3) {
+        const long lower = cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz - 1, g.n[2]));
+        lower_face_flux<D, R, 2>(U, face, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(2 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    if (!ok) *err = ERR_NONPHYSICAL;
+}
+
+// ----------------------------------------------------------------- update ---
+template <int D>
+__global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar, const double *__restrict__ U0,
+                                                const double *__restrict__ Uin, double *__restrict__ out, Geom g,
+                                                int stage, double dt)
+{
+    constexpr int NV = D + 2;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
+    const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
+    long up[3];
+    up[0] = wrapi(cx + 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
+    up[1] = cx + (long)g.n[0] * (wrapi(cy + 1, g.n[1]) + (long)g.n[1] * cz);
+    up[2] = D == 3 ? cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz + 1, g.n[2])) : 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double Fp = fbar[(a * NV + v) * g.ncell + up[a]];
+            const double Fm = fbar[(a * NV + v) * g.ncell + cell];
+            acc -= (Fp - Fm) / g.dx[a];
+        }
+        const long i = v * g.ncell + cell;
+        double r;
+        if (stage == 0) r = acc;
+        else if (stage == 1) r = Uin[i] + dt * acc;
+        else if (stage == 2) r = 0.75 * U0[i] + 0.25 * (Uin[i] + dt * acc);
+        else r = U0[i] / 3.0 + 2.0 / 3.0 * (Uin[i] + dt * acc);
+        out[i] = r;
+    }
+}
+
+// ------------------------------------------------------------ face states ---
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_states(const double *__restrict__ U, const double *__restrict__ face,
+                                                const double *__restrict__ theta, double *__restrict__ states,
+                                                Geom g)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NPTS = S::NPTS;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = U[v * g.ncell + cell];
+    const double tr = theta[cell], tp = theta[g.ncell + cell];
+#pragma unroll 1
+    for (int s = 0; s < NPTS; ++s) {
+        double w[NV], u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
+        limited_state<D>(ref, g.gamma, w, tr, tp, u);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) states[(cell * NPTS + s) * NV + v] = u[v];
+    }
+}
+
+// -------------------------------------------------------------------- CFL ---
+template <int D>
+__global__ __launch_bounds__(256) void k_cfl_partial(const double *__restrict__ U, double *__restrict__ part,
+                                                     int *__restrict__ err, Geom g)
+{
+    constexpr int NV = D + 2;
+    __shared__ double red[256 / 64];
+    double m = 0.0;
+    for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell;
+         cell += (long)gridDim.x * blockDim.x) {
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + cell];
+        if (!admissible<D>(u, g.gamma)) { *err = ERR_NONPHYSICAL; continue; }
+        const double cs = sqrt(g.gamma * pressure<D>(u, g.gamma) / u[0]);
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) s += (fabs(u[1 + a] / u[0]) + cs) / g.dx[a];
+        m = fmax(m, s);
+    }
+    // wave64 max, then across the block's waves
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+#pragma unroll
+        for (int i = 1; i < 256 / 64; ++i) r = fmax(r, red[i]);
+        part[blockIdx.x] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cfl_final(const double *__restrict__ part, int nparts, double cfl,
+                                                   double *__restrict__ dt)
+{
+    __shared__ double red[256 / 64];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, part[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+#pragma unroll
+        for (int i = 1; i < 256 / 64; ++i) r = fmax(r, red[i]);
+        *dt = cfl / r;
+    }
+}
+
+template <int D, int R>
+hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter &lim, int riemann,
+                    const double *U0, const double *Uin, double *out, int stage, double dt, hipStream_t s,
+                    const Timing &tm)
+{
+    auto mark = [&](int kind, int begin) { if (tm.on) tm.record(tm.self, kind, s, begin); };
+    using C = Cfg<D, R>;
+    const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
+                      (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
+    const long grid = ((nblk + 7) / 8) * 8;   // every XCD gets the same number of slots
+    mark(KT_RECON, 1);
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, Uin, t.w, w.face, w.theta, w.err,
+                       w.flags_in, g, lim);
+    mark(KT_RECON, 0);
+    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
+    mark(KT_FLUX, 1);
+    hipLaunchKernelGGL((k_flux<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.face, w.theta, w.fbar, w.err, g, riemann);
+    mark(KT_FLUX, 0);
+    mark(KT_UPDATE, 1);
+    hipLaunchKernelGGL((k_update<D>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
+    mark(KT_UPDATE, 0);
+    return hipGetLastError();
+}
+
+template <int D, int R>
+hipError_t states_impl(const Geom &g, const Tables &t, const Work &w, const Limiter &lim, const double *U,
+                       double *states, hipStream_t s)
+{
+    using C = Cfg<D, R>;
+    const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
+                      (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
+    const long grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, w.face, w.theta, w.err,
+                       w.flags_in, g, lim);
+    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
+    hipLaunchKernelGGL((k_states<D, R>), dim3(nb), dim3(256), 0, s, U, w.face, w.theta, states, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                           int riemann, const double *U0, const double *Uin, double *out, int stage, double dt,
+                           hipStream_t s, const Timing &tm)
+{
+    if (dim == 2 && R == 2) return rhs_impl<2, 2>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
+    if (dim == 2 && R == 3) return rhs_impl<2, 3>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
+    if (dim == 3 && R == 2) return rhs_impl<3, 2>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
+    if (dim == 3 && R == 3) return rhs_impl<3, 3>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                              const double *U, double *states, hipStream_t s)
+{
+    if (dim == 2 && R == 2) return states_impl<2, 2>(g, t, w, lim, U, states, s);
+    if (dim == 2 && R == 3) return states_impl<2, 3>(g, t, w, lim, U, states, s);
+    if (dim == 3 && R == 2) return states_impl<3, 2>(g, t, w, lim, U, states, s);
+    if (dim == 3 && R == 3) return states_impl<3, 3>(g, t, w, lim, U, states, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
+                      hipStream_t s)
+{
+    const int nparts = 1024;
+    if (dim == 2)
+        hipLaunchKernelGGL((k_cfl_partial<2>), dim3(nparts), dim3(256), 0, s, U, w.cfl_part, w.err, g);
+    else
+        hipLaunchKernelGGL((k_cfl_partial<3>), dim3(nparts), dim3(256), 0, s, U, w.cfl_part, w.err, g);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, s, w.cfl_part, nparts, cfl, dt_dev);
+    return hipGetLastError();
+}
+
+}  // namespace kfvm

@@ -1,0 +1,125 @@
+// Compile-time description of the KFVM-WENO stencils (paper section 3.1) and
+// of the per-cell reconstruction targets (section 5.1), for radius R in d
+// dimensions.  Used by the host weight builder and by the HIP kernels, which
+// unroll every loop over these tables so that offsets and member indices
+// become immediate operands.
+//
+//  * S0 = { i in Z^d : |i|^2 <= R^2 }, cells in lexicographic order of the
+//    offset tuple (x, y[, z]) with x slowest;
+//  * stencil 0 is S0, stencil 1 the ball of radius R-1, stencils 2.. the
+//    biased cones along +x, -x, +y, -y, +z, -z: the cells of S0 whose other
+//    coordinates are bounded in magnitude by the signed leading coordinate;
+//  * each stencil's table has n_pts face-point rows then n_der derivative
+//    rows, N_q columns in the stencil's member order;
+//  * face point s = (2 a + side) * R^(d-1) + g (normal axis a, side 0 = lower
+//    face, g the Gauss index over the transverse axes, first one slowest);
+//  * derivative multi-indices 0 < |alpha| <= R (section 3.3), by degree, then
+//    lexicographically descending.
+#pragma once
+
+namespace kfvm {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+constexpr int count_ball(int d, int r2, int R)
+{
+    int c = 0;
+    for (int i = -R; i <= R; ++i)
+        for (int j = -R; j <= R; ++j)
+            for (int k = (d == 3 ? -R : 0); k <= (d == 3 ? R : 0); ++k)
+                if (i * i + j * j + k * k <= r2) ++c;
+    return c;
+}
+
+constexpr int count_derivs(int d, int R)
+{
+    int c = 0;
+    for (int i = 0; i <= R; ++i)
+        for (int j = 0; j <= R; ++j)
+            for (int k = 0; k <= (d == 3 ? R : 0); ++k) {
+                int s = i + j + k;
+                if (s > 0 && s <= R) ++c;
+            }
+    return c;
+}
+
+template <int D, int R>
+struct Stencil {
+    static constexpr int N0 = count_ball(D, R * R, R);
+    static constexpr int NST = 2 + 2 * D;
+    static constexpr int NG = ipow(R, D - 1);        // Gauss points per face
+    static constexpr int NPTS = 2 * D * NG;          // face points per cell
+    static constexpr int NDER = count_derivs(D, R);  // derivative rows
+    static constexpr int NROWS = NPTS + NDER;
+    static constexpr int NV = D + 2;                 // conserved variables
+
+    int off[N0][3];          // unit-cell offsets (z = 0 in 2D)
+    int nmem[NST];           // cells per stencil
+    int mem[NST][N0];        // member indices into S0
+    int tab[NST];            // start of each stencil's table in the packed array
+    int tab_total;           // doubles in the packed array
+    int der[NDER][3];        // derivative multi-indices
+    int degree[NST];         // polynomial degree of the augmentation
+
+    constexpr Stencil() : off{}, nmem{}, mem{}, tab{}, tab_total(0), der{}, degree{}
+    {
+        int c = 0;
+        for (int i = -R; i <= R; ++i)
+            for (int j = -R; j <= R; ++j)
+                for (int k = (D == 3 ? -R : 0); k <= (D == 3 ? R : 0); ++k)
+                    if (i * i + j * j + k * k <= R * R) {
+                        off[c][0] = i; off[c][1] = j; off[c][2] = k;
+                        ++c;
+                    }
+        for (int q = 0; q < NST; ++q) {
+            int m = 0;
+            for (int h = 0; h < N0; ++h) {
+                int o[3] = {off[h][0], off[h][1], off[h][2]};
+                bool in = false;
+                if (q == 0) {
+                    in = true;
+                } else if (q == 1) {
+                    in = o[0] * o[0] + o[1] * o[1] + o[2] * o[2] <= (R - 1) * (R - 1);
+                } else {
+                    int a = (q - 2) / 2, sg = ((q - 2) % 2 == 0) ? 1 : -1;
+                    int lead = sg * o[a];
+                    in = true;
+                    for (int b = 0; b < D; ++b)
+                        if (b != a && (o[b] < 0 ? -o[b] : o[b]) > lead) in = false;
+                    if (lead < 0) in = false;
+                }
+                if (in) mem[q][m++] = h;
+            }
+            nmem[q] = m;
+        }
+        int t = 0;
+        for (int q = 0; q < NST; ++q) {
+            tab[q] = t;
+            t += NROWS * nmem[q];
+        }
+        tab_total = t;
+        int n = 0;
+        for (int deg = 1; deg <= R; ++deg)
+            for (int i = deg; i >= 0; --i)
+                for (int j = deg - i; j >= 0; --j) {
+                    int k = deg - i - j;
+                    if (D == 2 && k != 0) continue;
+                    der[n][0] = i; der[n][1] = j; der[n][2] = k;
+                    ++n;
+                }
+        // largest unisolvent degree: 2R-1 on S0, 2R-3 on the inner ball and
+        // R-1 on the cones (exact-rank result for R = 2, 3 in 2D and 3D)
+        degree[0] = 2 * R - 1;
+        degree[1] = 2 * R - 3;
+        for (int q = 2; q < NST; ++q) degree[q] = R - 1;
+    }
+};
+
+// linear weights of section 3.2 (gamma_hi = gamma_lo = 0.8)
+template <int D>
+constexpr double linear_weight(int q)
+{
+    return q == 0 ? 0.8 : (q == 1 ? 0.2 * 0.8 : 0.2 * 0.2 / (2 * D));
+}
+
+}  // namespace kfvm

@@ -1,0 +1,241 @@
+"""Python binding of libkfvm.so (include/kfvm.h): argument marshalling only.
+
+Every step of the right-hand side runs in the library's HIP kernels; torch is
+used for device memory and the current stream.  There is no fallback: if the
+library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkfvm.so")
+
+KFVM_OK, KFVM_ERR_ARG, KFVM_ERR_HIP, KFVM_ERR_NONPHYSICAL, KFVM_ERR_STATE = 0, -1, -2, -3, -4
+KFVM_FP64, KFVM_SPLIT_F16, KFVM_SPLIT_BF16 = 0, 1, 2
+KFVM_HLLC, KFVM_HLL = 0, 1
+
+EXPORTED = [
+    "kfvm_init", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream", "kfvm_set_precision",
+    "kfvm_set_limiter", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
+    "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
+    "kfvm_set_timing", "kfvm_kernel_times",
+]
+KERNEL_CLASSES = ("recon", "flux", "update")
+
+
+class KfvmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kfvm error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3)]
+
+
+class _Weights(C.Structure):
+    _fields_ = [("dim", C.c_int), ("R", C.c_int), ("n0", C.c_int), ("offsets", C.POINTER(C.c_int)),
+                ("n_stencils", C.c_int), ("stencil_ptr", C.POINTER(C.c_int)),
+                ("members", C.POINTER(C.c_int)), ("n_pts", C.c_int), ("n_der", C.c_int),
+                ("tables", C.POINTER(C.c_double)), ("gamma_lin", C.POINTER(C.c_double))]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("limiter_cells", C.c_longlong), ("weno_cell_vars", C.c_longlong),
+                ("cell_vars", C.c_longlong), ("error", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libkfvm.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2401_16543_amd.build`")
+    lib = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    sig = {
+        "kfvm_init": ([C.POINTER(vp), C.POINTER(_Mesh), ip, C.c_double, C.POINTER(_Weights)], ip),
+        "kfvm_rhs": ([vp, vp, vp], ip),
+        "kfvm_step": ([vp, vp, C.c_double], ip),
+        "kfvm_cfl_dt": ([vp, vp, C.c_double, dp], ip),
+        "kfvm_set_stream": ([vp, vp], ip),
+        "kfvm_set_precision": ([vp, ip], ip),
+        "kfvm_set_limiter": ([vp, ip, C.c_double], ip),
+        "kfvm_set_riemann": ([vp, ip], ip),
+        "kfvm_set_checking": ([vp, ip], ip),
+        "kfvm_status": ([vp], ip),
+        "kfvm_stats": ([vp, C.POINTER(_Stats)], ip),
+        "kfvm_face_states": ([vp, vp, vp], ip),
+        "kfvm_weights_build": ([ip, ip, C.c_double, dp, ip], ip),
+        "kfvm_weights_size": ([ip, ip], ip),
+        "kfvm_last_error": ([vp], C.c_char_p),
+        "kfvm_set_timing": ([vp, ip], ip),
+        "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
+        "kfvm_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes, f.restype = args, res
+    _lib = lib
+    return lib
+
+
+def weights_build(dim: int, R: int, ell_hat: float = 5.0):
+    """The library's binary128 reconstruction tables, packed as in kfvm.h (host only)."""
+    import numpy as np
+    lib = load_library()
+    n = lib.kfvm_weights_size(dim, R)
+    if n < 0:
+        raise KfvmError(n, "unsupported (dim, R)")
+    out = np.zeros(n)
+    rc = lib.kfvm_weights_build(dim, R, ell_hat, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+    if rc != n:
+        raise KfvmError(rc, "weight build failed")
+    return out
+
+
+class KFVM:
+    """One context of the library for a periodic box; U tensors are float64 on the GPU,
+    shaped (nvar, ny, nx) in 2D or (nvar, nz, ny, nx) in 3D."""
+
+    def __init__(self, dim: int, n, dx=None, order: int = 5, gamma: float = 1.4, weights=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("KFVM needs a ROCm GPU; none is visible")
+        self.lib = load_library()
+        n = list(n)
+        if len(n) != dim:
+            raise ValueError("len(n) must equal dim")
+        dx = list(dx) if dx is not None else [1.0 / x for x in n]
+        self.dim, self.n, self.dx, self.order, self.gamma = dim, n, dx, order, gamma
+        self.R = 2 if order == 5 else 3
+        self.nvar = dim + 2
+        self.shape = (self.nvar,) + tuple(reversed(n))
+        mesh = _Mesh()
+        mesh.dim = dim
+        mesh.n[:] = n + [1] * (3 - dim)
+        mesh.dx[:] = dx + [1.0] * (3 - dim)
+        wp = C.POINTER(_Weights)()
+        self._keep = None
+        if weights is not None:
+            wp, self._keep = self._pack_weights(weights)
+        h = C.c_void_p()
+        rc = self.lib.kfvm_init(C.byref(h), C.byref(mesh), order, gamma, wp)
+        if rc != KFVM_OK:
+            raise KfvmError(rc, self.lib.kfvm_last_error(None).decode())
+        self._h = h
+
+    @staticmethod
+    def _pack_weights(T):
+        """Marshal a dict with s0, members, weights (list of [rows, N_q]), n_pts, n_der, gamma."""
+        import numpy as np
+        d = T["s0"].shape[1]
+        off = np.ascontiguousarray(T["s0"].reshape(-1), dtype=np.int32)
+        mem = np.ascontiguousarray(np.concatenate(T["members"]), dtype=np.int32)
+        ptr = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(m) for m in T["members"]])]),
+                                   dtype=np.int32)
+        tab = np.ascontiguousarray(np.concatenate([w.reshape(-1) for w in T["weights"]]), dtype=np.float64)
+        gam = np.ascontiguousarray(T["gamma"], dtype=np.float64)
+        w = _Weights()
+        w.dim, w.R, w.n0 = d, int(T["R"]), len(T["s0"])
+        w.offsets = off.ctypes.data_as(C.POINTER(C.c_int))
+        w.n_stencils = len(T["members"])
+        w.stencil_ptr = ptr.ctypes.data_as(C.POINTER(C.c_int))
+        w.members = mem.ctypes.data_as(C.POINTER(C.c_int))
+        w.n_pts, w.n_der = int(T["n_pts"]), int(T["n_der"])
+        w.tables = tab.ctypes.data_as(C.POINTER(C.c_double))
+        w.gamma_lin = gam.ctypes.data_as(C.POINTER(C.c_double))
+        return C.pointer(w), (off, mem, ptr, tab, gam, w)
+
+    # -- plumbing -------------------------------------------------------------
+    def _check(self, rc):
+        if rc != KFVM_OK:
+            raise KfvmError(rc, self.lib.kfvm_last_error(self._h).decode())
+
+    def _stream(self):
+        self._check(self.lib.kfvm_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def _state(self, U):
+        if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float64 and U.is_contiguous()):
+            raise TypeError("U must be a contiguous float64 CUDA tensor")
+        if tuple(U.shape) != self.shape:
+            raise ValueError(f"U must have shape {self.shape}, got {tuple(U.shape)}")
+        return C.c_void_p(U.data_ptr())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.kfvm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ---------------------------------------------------------
+    def rhs(self, U, out=None):
+        if out is None:
+            out = torch.empty_like(U)
+        self._stream()
+        self._check(self.lib.kfvm_rhs(self._h, self._state(U), self._state(out)))
+        return out
+
+    def step(self, U, dt: float):
+        self._stream()
+        self._check(self.lib.kfvm_step(self._h, self._state(U), float(dt)))
+        return U
+
+    def cfl_dt(self, U, cfl: float) -> float:
+        self._stream()
+        dt = C.c_double()
+        self._check(self.lib.kfvm_cfl_dt(self._h, self._state(U), float(cfl), C.byref(dt)))
+        return dt.value
+
+    def face_states(self, U):
+        npts = 2 * self.dim * self.R ** (self.dim - 1)
+        ncell = 1
+        for x in self.n:
+            ncell *= x
+        out = torch.empty((ncell, npts, self.nvar), dtype=torch.float64, device=U.device)
+        self._stream()
+        self._check(self.lib.kfvm_face_states(self._h, self._state(U), C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_limiter(self, enabled: bool, kappa: float = 0.5):
+        self._check(self.lib.kfvm_set_limiter(self._h, int(enabled), float(kappa)))
+
+    def set_riemann(self, solver: str):
+        self._check(self.lib.kfvm_set_riemann(self._h, {"hllc": KFVM_HLLC, "hll": KFVM_HLL}[solver]))
+
+    def set_precision(self, mode: str):
+        self._check(self.lib.kfvm_set_precision(
+            self._h, {"fp64": KFVM_FP64, "split_f16": KFVM_SPLIT_F16, "split_bf16": KFVM_SPLIT_BF16}[mode]))
+
+    def set_checking(self, on: bool):
+        self._check(self.lib.kfvm_set_checking(self._h, int(on)))
+
+    def status(self):
+        return self.lib.kfvm_status(self._h)
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.kfvm_set_timing(self._h, int(on)))
+
+    def kernel_times(self) -> dict:
+        """{kernel class: (total ms, launches)} since the last call."""
+        ms = (C.c_double * 3)()
+        n = (C.c_longlong * 3)()
+        self._check(self.lib.kfvm_kernel_times(self._h, ms, n, 3))
+        return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def stats(self) -> dict:
+        s = _Stats()
+        self._check(self.lib.kfvm_stats(self._h, C.byref(s)))
+        return dict(limiter_cells=s.limiter_cells, weno_cell_vars=s.weno_cell_vars, cell_vars=s.cell_vars,
+                    error=s.error)
