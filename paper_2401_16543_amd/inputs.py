@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-_SLAB_POINTS = 1 << 24   # quadrature points evaluated per slab
+_SLAB_POINTS = 1 << 22   # quadrature points evaluated per slab
 
 
 @dataclass
@@ -121,8 +121,9 @@ def _primitive(spec: FieldSpec, X: torch.Tensor, gamma: float):
     out = []
     for j in range(d + 2):
         k, a, phi = (torch.as_tensor(t, dtype=torch.float64, device=X.device) for t in spec.modes[j])
-        arg = 2.0 * math.pi * (X @ k.T) + phi            # [P, M]
-        out.append(spec.base[j] + spec.amp[j] * (torch.sin(arg) @ a))
+        # elementwise products and sums (no BLAS: its gemv rejects very tall operands)
+        arg = 2.0 * math.pi * (X[:, None, :] * k[None, :, :]).sum(-1) + phi   # [P, M]
+        out.append(spec.base[j] + spec.amp[j] * (torch.sin(arg) * a).sum(-1))
     V = torch.stack(out)
     for kind, prm, r_rho, r_p in spec.regions:
         if kind == "ball":
@@ -134,7 +135,7 @@ def _primitive(spec: FieldSpec, X: torch.Tensor, gamma: float):
         else:
             nrm, offset, half = prm
             nv = torch.as_tensor(nrm, dtype=torch.float64, device=X.device)
-            s = X @ nv - offset
+            s = (X * nv).sum(-1) - offset
             s = s - torch.round(s)
             inside = s.abs() < half
         V[0] = torch.where(inside, V[0] * r_rho, V[0])
