@@ -158,6 +158,13 @@ int kfvm_weights_build(int dim, int R, double ell_hat, double *tables, int capac
 /* Number of float64 in the tables of (dim, R), or a negative code. */
 int kfvm_weights_size(int dim, int R);
 
+/* Per-(variable, cell) reconstruction choice, a caller-owned device array
+ * flags[nvar][ncells] of bytes: nonzero = WENO-AO (section 3.2), 0 = the linear
+ * full-stencil value (what a troubled-cell gate decides; section 3.5 describes
+ * the paper's own indicator).  NULL (the default) = WENO-AO everywhere.  The
+ * array must stay valid while work that reads it is queued. */
+int kfvm_set_flags(kfvm_ctx *ctx, const uint8_t *flags);
+
 /* on != 0: bracket every subsequent kernel launch with HIP events on the
  * context's stream (adds a few microseconds per launch). */
 int kfvm_set_timing(kfvm_ctx *ctx, int on);

@@ -29,6 +29,10 @@ struct kfvm_ctx {
     int timing = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
     hipEvent_t pending[kfvm::KT_COUNT] = {};
+    // split-precision path
+    std::vector<double> host_tables;
+    uint4 *d_mix_full = nullptr, *d_mix_lin = nullptr;
+    int mix_sw = 0, mix_mode = -1;
 };
 
 namespace {
@@ -110,6 +114,108 @@ int sync_check(kfvm_ctx *c)
     return KFVM_OK;
 }
 
+uint16_t to_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+double from_bf16(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+uint16_t to_f16(double x)
+{
+    _Float16 h = (_Float16)x;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+double from_f16(uint16_t u)
+{
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return (double)h;
+}
+
+// Lay the float64 tables out as matrix-core operands (see rhs_mixed.hip):
+// slot (tile t, k-step ks, hi/lo, lane) holds A[32 t + lane % 32][16 ks + 8 (lane / 32) + i], i < 8.
+template <int D, int R>
+void build_operands(const double *tab, bool bf16, int sw, std::vector<uint16_t> &full, std::vector<uint16_t> &lin)
+{
+    constexpr kfvm::Stencil<D, R> st{};
+    using S = kfvm::Stencil<D, R>;
+    constexpr int KS = (S::N0 + 15) / 16, NTF = (S::NROWS * 8 + 31) / 32, NTL = (S::NPTS + 31) / 32;
+    int pos[S::NST][S::N0];
+    for (int q = 0; q < S::NST; ++q) {
+        for (int h = 0; h < S::N0; ++h) pos[q][h] = -1;
+        for (int j = 0; j < st.nmem[q]; ++j) pos[q][st.mem[q][j]] = j;
+    }
+    auto put = [&](std::vector<uint16_t> &dst, int t, int ks, int lane, int i, double w) {
+        const double x = std::ldexp(w, sw);
+        const uint16_t hi = bf16 ? to_bf16(x) : to_f16(x);
+        const double xh = bf16 ? from_bf16(hi) : from_f16(hi);
+        const uint16_t lo = bf16 ? to_bf16(x - xh) : to_f16(x - xh);
+        dst[((((size_t)t * KS + ks) * 2 + 0) * 64 + lane) * 8 + i] = hi;
+        dst[((((size_t)t * KS + ks) * 2 + 1) * 64 + lane) * 8 + i] = lo;
+    };
+    full.assign((size_t)NTF * KS * 2 * 64 * 8, 0);
+    lin.assign((size_t)NTL * KS * 2 * 64 * 8, 0);
+    for (int t = 0; t < NTF; ++t)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int i = 0; i < 8; ++i) {
+                    const int row = 32 * t + lane % 32, k = 16 * ks + 8 * (lane / 32) + i;
+                    const int tau = row / 8, q = row % 8;
+                    double w = 0.0;
+                    if (q < S::NST && tau < S::NROWS && k < S::N0 && pos[q][k] >= 0)
+                        w = tab[st.tab[q] + tau * st.nmem[q] + pos[q][k]];
+                    put(full, t, ks, lane, i, w);
+                }
+    for (int t = 0; t < NTL; ++t)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int i = 0; i < 8; ++i) {
+                    const int tau = 32 * t + lane % 32, k = 16 * ks + 8 * (lane / 32) + i;
+                    const double w = (tau < S::NPTS && k < S::N0) ? tab[st.tab[0] + tau * S::N0 + k] : 0.0;
+                    put(lin, t, ks, lane, i, w);
+                }
+}
+
+int prepare_mixed(kfvm_ctx *c, int mode)
+{
+    if (c->mix_mode == mode) return KFVM_OK;
+    const bool bf16 = mode == KFVM_SPLIT_BF16;
+    double wmax = 0.0;
+    for (double x : c->host_tables) wmax = std::fmax(wmax, std::fabs(x));
+    // largest power-of-two scale that keeps every scaled weight below 30000 (fp16 max 65504)
+    const int sw = (int)std::floor(std::log2(30000.0 / wmax));
+    std::vector<uint16_t> full, lin;
+    if (c->dim == 2 && c->R == 2) build_operands<2, 2>(c->host_tables.data(), bf16, sw, full, lin);
+    else if (c->dim == 2 && c->R == 3) build_operands<2, 3>(c->host_tables.data(), bf16, sw, full, lin);
+    else build_operands<3, 2>(c->host_tables.data(), bf16, sw, full, lin);
+    if (!c->d_mix_full) {
+        int rc = alloc(c, (void **)&c->d_mix_full, full.size() * 2);
+        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_mix_lin, lin.size() * 2);
+        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->work.inc32,
+                                      sizeof(float) * (size_t)npts_of(c->dim, c->R) * c->nvar * c->geom.ncell);
+        if (rc != KFVM_OK) return rc;
+    }
+    HIP_TRY(c, hipMemcpy(c->d_mix_full, full.data(), full.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_mix_lin, lin.data(), lin.size() * 2, hipMemcpyHostToDevice));
+    c->mix_sw = sw;
+    c->mix_mode = mode;
+    return KFVM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +280,7 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
         kfvm_destroy(c);
         return rc;
     }
+    c->host_tables = host;
     hipError_t e = hipMemcpy(c->d_tables, host.data(), sizeof(double) * ntab, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->work.err, 0, sizeof(int) * 4);
     if (e != hipSuccess) {
@@ -203,9 +310,16 @@ static kfvm::Timing timing_of(kfvm_ctx *c) { return kfvm::Timing{c->timing, reco
 
 static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
 {
-    kfvm::Tables t{c->d_tables};
-    hipError_t e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage,
-                                         dt, c->stream, timing_of(c));
+    hipError_t e;
+    if (c->precision == KFVM_FP64) {
+        kfvm::Tables t{c->d_tables};
+        e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage, dt,
+                                  c->stream, timing_of(c));
+    } else {
+        kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
+        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
+                                   c->riemann, U0, Uin, out, stage, dt, nullptr, c->stream, timing_of(c));
+    }
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return KFVM_OK;
 }
@@ -254,7 +368,14 @@ int kfvm_set_stream(kfvm_ctx *c, void *s)
 int kfvm_set_precision(kfvm_ctx *c, int mode)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
-    if (mode != KFVM_FP64) return fail(c, KFVM_ERR_ARG, "precision mode not available in this build");
+    if (mode != KFVM_FP64 && mode != KFVM_SPLIT_F16 && mode != KFVM_SPLIT_BF16)
+        return fail(c, KFVM_ERR_ARG, "unknown precision mode");
+    if (mode != KFVM_FP64) {
+        if (!kfvm::mixed_supported(c->dim, c->R))
+            return fail(c, KFVM_ERR_ARG, "split precision is not available for 3D R = 3");
+        const int rc = prepare_mixed(c, mode);
+        if (rc != KFVM_OK) return rc;
+    }
     c->precision = mode;
     return KFVM_OK;
 }
@@ -307,10 +428,24 @@ int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     if (!U || !states) return fail(c, KFVM_ERR_ARG, "null buffer");
-    kfvm::Tables t{c->d_tables};
-    hipError_t e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
+    hipError_t e;
+    if (c->precision == KFVM_FP64) {
+        kfvm::Tables t{c->d_tables};
+        e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
+    } else {
+        kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
+        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
+                                   c->riemann, U, U, nullptr, 0, 0.0, states, c->stream, kfvm::Timing{0, nullptr, nullptr});
+    }
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return c->checking ? sync_check(c) : KFVM_OK;
+}
+
+int kfvm_set_flags(kfvm_ctx *c, const uint8_t *flags)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    c->work.flags_in = flags;
+    return KFVM_OK;
 }
 
 int kfvm_set_timing(kfvm_ctx *c, int on)

@@ -28,6 +28,15 @@ struct Work {
     int *err;          // sticky device error code
     uint32_t *counts;  // [2] limiter cells, WENO (cell, var) pairs
     const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
+    float *inc32;      // [n_pts][nvar][ncell] blended increments w_s - W_c (split-precision path)
+};
+
+// Matrix-core operands of the split-precision path, in the per-lane layout of
+// v_mfma_f32_32x32x16: [tile][k-step][hi, lo][lane] slots of 8 16-bit values.
+struct MixTables {
+    const uint4 *full;   // every stencil, rows interleaved as target * 8 + stencil
+    const uint4 *lin;    // S0 face-point rows only
+    int sw;              // weights are scaled by 2^sw
 };
 
 struct Tables {
@@ -48,6 +57,13 @@ struct Timing {
 hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
                            int riemann, const double *U0, const double *Uin, double *out, int stage, double dt,
                            hipStream_t s, const Timing &tm);
+hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0, const double *Uin, double *out,
+                         int stage, double dt, hipStream_t s);
+bool mixed_supported(int dim, int R);
+int mixed_operand_slots(int dim, int R, int which);   // which: 0 full, 1 lin; 16-byte slots
+hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixTables &t, const Work &w,
+                            const Limiter &lim, int riemann, const double *U0, const double *Uin, double *out,
+                            int stage, double dt, double *states, hipStream_t s, const Timing &tm);
 hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,

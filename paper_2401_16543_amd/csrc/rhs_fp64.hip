@@ -20,167 +20,11 @@
 // All arrays are struct-of-arrays over cells so that every global access is
 // coalesced along x.  Blocks are remapped so that each XCD owns a contiguous
 // run of tiles, which keeps halo re-reads in that XCD's L2.
-#include "kernels.hpp"
-#include "stencil.hpp"
-
-#include <utility>
+#include "device_common.hpp"
 
 namespace kfvm {
 namespace {
-
-constexpr double EPS_WENO = 1e-40;
-constexpr int ERR_NONPHYSICAL = -3;
-
-template <int D, int R>
-struct Cfg {
-    using S = Stencil<D, R>;
-    static constexpr S st{};
-    static constexpr int TX = D == 2 ? 16 : 8;
-    static constexpr int TY = D == 2 ? 16 : 8;
-    static constexpr int TZ = D == 2 ? 1 : 4;
-    static constexpr int NT = TX * TY * TZ;
-    static constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = D == 3 ? TZ + 2 * R : 1;
-    static constexpr int HN = HX * HY * HZ;
-    static constexpr int NV = D + 2;
-};
-
-// linear weights, evaluated as (1 - g_hi) g_lo and (1 - g_hi)(1 - g_lo) / (2 D)
-template <int D>
-__device__ __forceinline__ double lin_w(int q)
-{
-    constexpr double ghi = 0.8, glo = 0.8;
-    return q == 0 ? ghi : (q == 1 ? (1.0 - ghi) * glo : (1.0 - ghi) * (1.0 - glo) / (2 * D));
-}
-
-// Blocks are handed to the 8 XCDs round-robin; give XCD k the k-th contiguous
-// eighth of the tiles so neighbouring tiles share an L2.
-__device__ __forceinline__ long xcd_tile(long bid, long nblk)
-{
-    const long per = (nblk + 7) / 8;
-    const long xcd = bid % 8, local = bid / 8;
-    const long t = xcd * per + local;
-    return t;    // may exceed nblk - 1 for the last XCD: caller checks
-}
-
-// i in [-n, 2n): one wrap (neighbour indices of in-range cells)
-__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// any i: full periodic reduction (halo of a tile can reach past 2n on small grids)
-__device__ __forceinline__ int wrap_any(int i, int n)
-{
-    const int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
-template <int D>
-__device__ __forceinline__ double pressure(const double *u, double gam)
-{
-    double ke = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) ke += u[1 + a] * u[1 + a];
-    ke = 0.5 * ke / u[0];
-    return (gam - 1.0) * (u[D + 1] - ke);
-}
-
-template <int D>
-__device__ __forceinline__ bool admissible(const double *u, double gam)
-{
-    bool ok = true;
-#pragma unroll
-    for (int v = 0; v < D + 2; ++v) ok = ok && isfinite(u[v]);
-    return ok && u[0] > 0.0 && pressure<D>(u, gam) > 0.0;
-}
-
-// Phi^-1 w for the reference state (eq. primMat; dE/du_i = rho u_i), dense
-// row order as a matrix-vector product.
-template <int D>
-__device__ __forceinline__ void phi_inv_apply(const double *ref, double gam, const double *w, double *u)
-{
-    constexpr int NV = D + 2, E = D + 1;
-    const double rho = ref[0];
-    double vel[D], uu = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
-    double M[NV][NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) M[i][j] = 0.0;
-    M[0][0] = 1.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        M[1 + a][0] = vel[a];
-        M[1 + a][1 + a] = rho;
-        M[E][1 + a] = rho * vel[a];
-    }
-    M[E][0] = uu / 2.0;
-    M[E][E] = 1.0 / (gam - 1.0);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) s += M[i][j] * w[j];
-        u[i] = s;
-    }
-}
-
-// Limited Riemann state: u = Phi^-1 w, then the density and pressure scalings
-// about the cell average, each only when it is active (section 4.2).
-template <int D>
-__device__ __forceinline__ void limited_state(const double *ref, double gam, const double *w, double th_rho,
-                                              double th_p, double *u)
-{
-    constexpr int NV = D + 2;
-    phi_inv_apply<D>(ref, gam, w, u);
-    if (th_rho < 1.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * (u[v] - ref[v]);
-    }
-    if (th_p < 1.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_p * (u[v] - ref[v]);
-    }
-}
-
-// ------------------------------------------------------------------ recon ---
-// Nonzero entries of Phi = dV/dU at the reference state (eq. consToLPMat).
-template <int D>
-struct PhiRows {
-    double inv_rho, m_vel[D], e0, e_mom[D], e_e;
-    __device__ __forceinline__ void init(const double *ref, double gam)
-    {
-        const double rho = ref[0];
-        double vel[D], uu = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
-        inv_rho = 1.0 / rho;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            m_vel[a] = -vel[a] / rho;
-            e_mom[a] = (1.0 - gam) * vel[a];
-        }
-        e0 = (gam - 1.0) * uu / 2.0;
-        e_e = gam - 1.0;
-    }
-};
-
-// Component K of W = Phi U at LDS index o, summed in the column order of the
-// dense product (zero entries skipped: adding an exact zero changes nothing).
-template <int D, int K, int HN>
-__device__ __forceinline__ double w_component(const double (*tile)[HN], int o, const PhiRows<D> &ph)
-{
-    if constexpr (K == 0) {
-        return tile[0][o];
-    } else if constexpr (K <= D) {
-        double s = ph.m_vel[K - 1] * tile[0][o];
-        return s + ph.inv_rho * tile[K][o];
-    } else {
-        double s = ph.e0 * tile[0][o];
-#pragma unroll
-        for (int a = 0; a < D; ++a) s += ph.e_mom[a] * tile[1 + a][o];
-        return s + ph.e_e * tile[D + 1][o];
-    }
-}
+using namespace dev;
 
 // Reconstruction of variable K of W at every face point of one cell: smoothness
 // indicators (eq. smoothIndic), nonlinear weights (eq. nlinWts) and the WENO-AO
@@ -383,94 +227,6 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     }
     theta[cell] = th_rho;
     theta[g.ncell + cell] = th_p;
-}
-
-// ----------------------------------------------------------------- Riemann ---
-template <int D>
-__device__ __forceinline__ void phys_flux(const double *u, int a, double p, double *F)
-{
-    const double un = u[1 + a] / u[0];
-    F[0] = u[1 + a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) F[1 + b] = u[1 + b] * un + (b == a ? p : 0.0);
-    F[D + 1] = un * (u[D + 1] + p);
-}
-
-// HLLC (Toro ch. 10) or HLL, wavespeeds of Batten et al. from Roe averages.
-template <int D, int A>
-__device__ __forceinline__ void riemann(const double *uL, const double *uR, double gam, int hll, double *F)
-{
-    constexpr int NV = D + 2, E = D + 1;
-    const double pL = pressure<D>(uL, gam), pR = pressure<D>(uR, gam);
-    const double rL = uL[0], rR = uR[0];
-    double vL[D], vR[D];
-#pragma unroll
-    for (int b = 0; b < D; ++b) { vL[b] = uL[1 + b] / rL; vR[b] = uR[1 + b] / rR; }
-    const double cL = sqrt(gam * pL / rL), cR = sqrt(gam * pR / rR);
-    const double HL = (uL[E] + pL) / rL, HR = (uR[E] + pR) / rR;
-    const double sL = sqrt(rL), sR = sqrt(rR);
-    double qt = 0.0, vtA = 0.0;
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-        const double vt = (sL * vL[b] + sR * vR[b]) / (sL + sR);
-        qt += vt * vt;
-        if (b == A) vtA = vt;
-    }
-    const double Ht = (sL * HL + sR * HR) / (sL + sR);
-    const double ct = sqrt((gam - 1.0) * (Ht - 0.5 * qt));
-    const double SL = fmin(vL[A] - cL, vtA - ct);
-    const double SR = fmax(vR[A] + cR, vtA + ct);
-    double FL[NV], FR[NV];
-    phys_flux<D>(uL, A, pL, FL);
-    phys_flux<D>(uR, A, pR, FR);
-    if (SL >= 0.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = FL[v];
-        return;
-    }
-    if (SR <= 0.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = FR[v];
-        return;
-    }
-    if (hll) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) / (SR - SL);
-        return;
-    }
-    const double Ss = (pR - pL + rL * vL[A] * (SL - vL[A]) - rR * vR[A] * (SR - vR[A]))
-                    / (rL * (SL - vL[A]) - rR * (SR - vR[A]));
-    const bool left = Ss >= 0.0;
-    const double SK = left ? SL : SR, rK = left ? rL : rR, pK = left ? pL : pR;
-    double uK[NV], FK[NV], vK[D];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) { uK[v] = left ? uL[v] : uR[v]; FK[v] = left ? FL[v] : FR[v]; }
-#pragma unroll
-    for (int b = 0; b < D; ++b) vK[b] = left ? vL[b] : vR[b];
-    const double fac = rK * (SK - vK[A]) / (SK - Ss);
-    double us[NV];
-    us[0] = fac;
-#pragma unroll
-    for (int b = 0; b < D; ++b) us[1 + b] = fac * (b == A ? Ss : vK[b]);
-    us[E] = fac * (uK[E] / rK + (Ss - vK[A]) * (Ss + pK / (rK * (SK - vK[A]))));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = FK[v] + SK * (us[v] - uK[v]);
-}
-
-// Gauss weight of transverse index gi: product over the transverse axes,
-// first factor from the fastest-varying index
-template <int D, int R>
-__device__ __forceinline__ double face_weight(int gi)
-{
-    const double w2[2] = {0.5, 0.5};
-    const double w3[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
-    double w = 1.0;
-#pragma unroll
-    for (int t = 0; t < D - 1; ++t) {
-        w *= R == 2 ? w2[gi % R] : w3[gi % R];
-        gi /= R;
-    }
-    return w;
 }
 
 // ------------------------------------------------------------------- flux ---
@@ -699,6 +455,15 @@ hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const
     if (dim == 3 && R == 2) return rhs_impl<3, 2>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
     if (dim == 3 && R == 3) return rhs_impl<3, 3>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0, const double *Uin, double *out,
+                         int stage, double dt, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
+    if (dim == 2) hipLaunchKernelGGL((k_update<2>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
+    else hipLaunchKernelGGL((k_update<3>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
+    return hipGetLastError();
 }
 
 hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,

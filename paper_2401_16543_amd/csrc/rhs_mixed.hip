@@ -1,0 +1,564 @@
+// Split-precision KFVM-WENO right-hand side for gfx950 (matrix cores).
+//
+// The weight-apply and smoothness-indicator contractions run on
+// v_mfma_f32_32x32x16_{f16,bf16}: each operand x is split into hi = half(x) and
+// lo = half(x - hi), and A.B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi is accumulated
+// in float32.  Everything around them stays in float64: the increments fed to
+// the matrix cores, the smoothness-indicator squares, the nonlinear weights and
+// their normalisation (eps = 1e-40 is far below the float32 range), the WENO-AO
+// blend, the positivity limiter, the Riemann solver and the Runge-Kutta update.
+//
+// Contraction layout (one wave = 32 cells, both half-waves on the same cells):
+//   B (K x N): the increments delta_h = W_h - W_c of one reconstruction variable
+//      over S0 (K, padded to 16), for the wave's 32 cells (N).  Because the point
+//      rows of every table sum to one and the derivative rows to zero, point
+//      values are W_c + R.delta and derivatives R.delta exactly; the increments
+//      are small on smooth data, so the split keeps ~22 significant bits of
+//      them.  They are scaled per cell by a power of two to [2^13, 2^14).
+//   A (M x K): every stencil's table embedded in S0 columns (zeros outside the
+//      stencil), rows interleaved as target * 8 + stencil, weights scaled by 2^SW.
+//      In the 32 x 32 accumulator layout a lane then holds, for each of four
+//      targets per tile, the values of four stencils (stencils 0-3 in the lower
+//      half-wave, 4-7 in the upper): the smoothness indicators and the blend are
+//      lane-local partial sums plus one exchange between the half-waves.
+//   A second table holds only the S0 face-point rows (targets as rows): a wave
+//   whose 32 cells the gate marks as smooth for a variable uses it alone.
+// The kernel writes the blended increments w_s - W_c as float32 (half the bytes
+// of the float64 path; the value is a float32 matrix-core sum to begin with),
+// and the limiter's two factors; the face-flux kernel rebuilds
+// u_s = U_c + theta Phi^-1 (w_s - W_c).
+#include "device_common.hpp"
+
+namespace kfvm {
+namespace {
+using namespace dev;
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int SB = 13;   // per-cell increment scale: max |delta| * 2^(SB - e) in [2^13, 2^14)
+
+template <int D, int R>
+struct MixCfg {
+    using S = Stencil<D, R>;
+    static constexpr int KS = (S::N0 + 15) / 16;               // k-steps of 16
+    static constexpr int NTF = (S::NROWS * 8 + 31) / 32;        // interleaved tiles
+    static constexpr int TP_END = (S::NPTS * 8 + 31) / 32;      // tiles holding point rows
+    static constexpr int TD_BEGIN = (S::NPTS * 8) / 32;         // first tile holding derivative rows
+    static constexpr int NTL = (S::NPTS + 31) / 32;             // S0-only tiles
+    static constexpr int A_FULL = NTF * KS * 2 * 64;            // 16-byte operand slots
+    static constexpr int A_LIN = NTL * KS * 2 * 64;
+    static constexpr int NT = 2 * Cfg<D, R>::NT;                // two lanes per cell
+};
+
+template <bool BF>
+__device__ __forceinline__ f16v mfma(uint4 a, uint4 b, f16v c)
+{
+    if constexpr (BF)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bh8, a), __builtin_bit_cast(bh8, b), c, 0, 0,
+                                                       0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+}
+
+// hi/lo split of a scaled increment into two 16-bit values (bit patterns)
+template <bool BF>
+__device__ __forceinline__ void split16(double y, uint16_t &hi, uint16_t &lo)
+{
+    if constexpr (BF) {
+        const __bf16 h = (__bf16)(float)y;
+        const __bf16 l = (__bf16)(float)(y - (double)(float)h);
+        hi = __builtin_bit_cast(uint16_t, h);
+        lo = __builtin_bit_cast(uint16_t, l);
+    } else {
+        const _Float16 h = (_Float16)(float)y;
+        const _Float16 l = (_Float16)(float)(y - (double)(float)h);
+        hi = __builtin_bit_cast(uint16_t, h);
+        lo = __builtin_bit_cast(uint16_t, l);
+    }
+}
+
+// increment of variable K at S0 point kk (0 for padding), LDS offset folded in
+template <int D, int R, int K>
+__device__ __forceinline__ double slot_increment(const double (*tile)[Cfg<D, R>::HN], int lc, int hf, int kA, int kB,
+                                                 const PhiRows<D> &ph, double Wc)
+{
+    using C = Cfg<D, R>;
+    constexpr int N0 = C::S::N0;
+    const int oA = kA < N0 ? C::st.off[kA][0] + C::HX * (C::st.off[kA][1] + C::HY * C::st.off[kA][2]) : 0;
+    const int oB = kB < N0 ? C::st.off[kB][0] + C::HX * (C::st.off[kB][1] + C::HY * C::st.off[kB][2]) : 0;
+    const bool valid = hf ? (kB < N0) : (kA < N0);
+    const int o = lc + (hf ? oB : oA);
+    const double w = w_component<D, K, C::HN>(tile, o, ph);
+    return valid ? w - Wc : 0.0;
+}
+
+template <int D, int R, int K, bool BF>
+__device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
+                                          const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                          float *__restrict__ inc, long cell, long ncell, bool active, int sw)
+{
+    using C = Cfg<D, R>;
+    using M = MixCfg<D, R>;
+    using S = typename C::S;
+    constexpr int NV = C::NV, NST = S::NST, NPTS = S::NPTS, NROWS = S::NROWS, KS = M::KS;
+    const int hf = lane >> 5;
+    const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
+
+    // increments over this lane's K slots: slot 16 ks + 8 hf + i
+    double dl[KS][8];
+    double amax = 0.0;
+    int lcc = lc;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            dl[ks][i] = slot_increment<D, R, K>(tile, lcc, hf, 16 * ks + i, 16 * ks + 8 + i, ph, Wc);
+            asm volatile("" : "+v"(dl[ks][i]));
+            amax = fmax(amax, fabs(dl[ks][i]));
+        }
+        asm volatile("" : "+v"(lcc) : "v"(dl[ks][7]));
+    }
+    amax = fmax(amax, __shfl_xor(amax, 32, 64));
+    int ex = 0;
+    if (amax > 0.0) frexp(amax, &ex);          // amax in [2^(ex-1), 2^ex)
+    const int e = ex - 1;
+    const double sc = ldexp(1.0, SB - e), unscale = ldexp(1.0, e - SB - sw);
+    uint4 bh[KS], bl[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        uint16_t h[8], l[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) split16<BF>(dl[ks][i] * sc, h[i], l[i]);
+        bh[ks] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16, h[4] | (uint32_t)h[5] << 16,
+                            h[6] | (uint32_t)h[7] << 16);
+        bl[ks] = make_uint4(l[0] | (uint32_t)l[1] << 16, l[2] | (uint32_t)l[3] << 16, l[4] | (uint32_t)l[5] << 16,
+                            l[6] | (uint32_t)l[7] << 16);
+    }
+
+    const bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    if (__any(use_weno && active)) {
+        // smoothness indicators: lane-local sums over its four stencils, then the partner's four
+        double bp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = M::TD_BEGIN; t < M::NTF; ++t) {
+            f16v acc = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const uint4 ah = As[((t * KS + ks) * 2 + 0) * 64 + lane];
+                const uint4 al = As[((t * KS + ks) * 2 + 1) * 64 + lane];
+                acc = mfma<BF>(ah, bh[ks], acc);
+                acc = mfma<BF>(ah, bl[ks], acc);
+                acc = mfma<BF>(al, bh[ks], acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int tau = 4 * t + j / 4;
+                if (tau >= NPTS && tau < NROWS) {
+                    const double dv = (double)acc[j] * unscale;
+                    bp[j % 4] += dv * dv;
+                }
+            }
+        }
+        double beta[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double other = __shfl_xor(bp[i], 32, 64);
+            beta[i] = hf ? other : bp[i];
+            beta[4 + i] = hf ? bp[i] : other;
+        }
+        // nonlinear weights (eq. nlinWts) and WENO-AO coefficients (eq. wenoAOrec) in FP64
+        double c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = q == 0 ? 1.0 : 0.0;
+        if (use_weno) {
+            double om[NST], sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < NST; ++q) {
+                om[q] = lin_w<D>(q) / (beta[q] * beta[q] + EPS_WENO);
+                sum += om[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NST; ++q) om[q] /= sum;
+            c[0] = om[0] / lin_w<D>(0);
+#pragma unroll
+            for (int q = 1; q < NST; ++q) c[q] = om[q] - om[0] * lin_w<D>(q) / lin_w<D>(0);
+        }
+        // this half-wave's four coefficients, selected as values (a select of two
+        // array elements would otherwise become a dynamically indexed private array)
+        double cm[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double a = c[i], b = c[4 + i];
+            asm volatile("" : "+v"(a), "+v"(b));
+            cm[i] = hf ? b : a;
+        }
+        // blended face-point increments
+#pragma unroll
+        for (int t = 0; t < M::TP_END; ++t) {
+            f16v acc = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const uint4 ah = As[((t * KS + ks) * 2 + 0) * 64 + lane];
+                const uint4 al = As[((t * KS + ks) * 2 + 1) * 64 + lane];
+                acc = mfma<BF>(ah, bh[ks], acc);
+                acc = mfma<BF>(ah, bl[ks], acc);
+                acc = mfma<BF>(al, bh[ks], acc);
+            }
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                const int tau = 4 * t + gq;
+                if (tau < NPTS) {
+                    double part = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) part += cm[i] * (double)acc[4 * gq + i];
+                    part *= unscale;
+                    const double tot = part + __shfl_xor(part, 32, 64);
+                    if ((tau & 1) == hf && active) inc[((long)tau * NV + K) * ncell + cell] = (float)tot;
+                }
+            }
+        }
+    } else {
+        // every cell of the wave is linear for this variable: S0 face rows only
+#pragma unroll
+        for (int t = 0; t < M::NTL; ++t) {
+            f16v acc = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const uint4 ah = Al[((t * KS + ks) * 2 + 0) * 64 + lane];
+                const uint4 al = Al[((t * KS + ks) * 2 + 1) * 64 + lane];
+                acc = mfma<BF>(ah, bh[ks], acc);
+                acc = mfma<BF>(ah, bl[ks], acc);
+                acc = mfma<BF>(al, bh[ks], acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int tau = 32 * t + 8 * (j / 4) + 4 * hf + j % 4;
+                // this lane owns tau; keep the ownership rule (tau & 1) == hf of the
+                // blended path by exchanging with the partner
+                const double v = (double)acc[j] * unscale;
+                const double other = __shfl_xor(v, 32, 64);
+                const int tau_o = 32 * t + 8 * (j / 4) + 4 * (1 - hf) + j % 4;
+                if (active) {
+                    if (tau < NPTS && (tau & 1) == hf) inc[((long)tau * NV + K) * ncell + cell] = (float)v;
+                    if (tau_o < NPTS && (tau_o & 1) == hf) inc[((long)tau_o * NV + K) * ncell + cell] = (float)other;
+                }
+            }
+        }
+    }
+}
+
+template <int D, int R, bool BF, int... K>
+__device__ __forceinline__ void mixed_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
+                                               const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
+                                               float *inc, long cell, long ncell, bool active, int sw,
+                                               std::integer_sequence<int, K...>)
+{
+    ((mixed_var<D, R, K, BF>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al, ph,
+                             flags, inc, cell, ncell, active, sw)),
+     ...);
+}
+
+// Phi^-1 applied to an increment vector (eq. primMat; dE/du_i = rho u_i)
+template <int D>
+struct PhiInv {
+    double rho, vel[D], uu2, inv_gm1;
+    __device__ __forceinline__ void init(const double *ref, double gam)
+    {
+        rho = ref[0];
+        double uu = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
+        uu2 = uu / 2.0;
+        inv_gm1 = 1.0 / (gam - 1.0);
+    }
+    __device__ __forceinline__ void apply(const double *w, double *u) const
+    {
+        u[0] = w[0];
+        double e = uu2 * w[0];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            u[1 + a] = vel[a] * w[0] + rho * w[1 + a];
+            e += rho * vel[a] * w[1 + a];
+        }
+        u[D + 1] = e + inv_gm1 * w[D + 1];
+    }
+};
+
+template <int D, int R, bool BF>
+__global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
+    const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
+    float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
+    Geom g, Limiter lim, int sw)
+{
+    using C = Cfg<D, R>;
+    using M = MixCfg<D, R>;
+    using S = typename C::S;
+    constexpr int NV = C::NV, NPTS = S::NPTS;
+    __shared__ double tile[NV][C::HN];
+    __shared__ uint4 As[M::A_FULL];
+    __shared__ uint4 Al[M::A_LIN];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long tb = xcd_tile(blockIdx.x, nblk);
+    if (tb >= nblk) return;
+    const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
+    const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+
+    for (int i = threadIdx.x; i < C::HN; i += M::NT) {
+        const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+        const int gx = wrap_any(x0 + hx, g.n[0]), gy = wrap_any(y0 + hy, g.n[1]);
+        const int gz = D == 3 ? wrap_any(z0 + hz, g.n[2]) : 0;
+        const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[v][i] = U[v * g.ncell + cl];
+    }
+    for (int i = threadIdx.x; i < M::A_FULL; i += M::NT) As[i] = Afull[i];
+    for (int i = threadIdx.x; i < M::A_LIN; i += M::NT) Al[i] = Alin[i];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;
+    const int ci = wave * 32 + (lane & 31);
+    const int tx = ci % C::TX, ty = (ci / C::TX) % C::TY, tz = ci / (C::TX * C::TY);
+    const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
+    const bool active = cx < g.n[0] && cy < g.n[1] && (D == 2 || cz < g.n[2]);
+    const long cell = active ? cx + (long)g.n[0] * (cy + (long)g.n[1] * cz) : 0;
+    const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
+
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
+    const double gam = g.gamma;
+    const bool ok = admissible<D>(ref, gam);
+    if (!ok && active) *err = ERR_NONPHYSICAL;
+    PhiRows<D> ph;
+    ph.init(ref, gam);
+    // every lane of the wave takes part in the matrix-core work; inactive and
+    // non-physical cells compute on their (finite or not) data and store nothing
+    mixed_all_vars<D, R, BF>(tile, lc, lane, As, Al, ph, flags, inc, cell, g.ncell, active && ok, sw,
+                             std::make_integer_sequence<int, NV>{});
+
+    double th_rho = 1.0, th_p = 1.0;
+    if (lim.on) {
+        double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+        bool nb_ok = true;
+#pragma unroll 1
+        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll 1
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll 1
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int o = lc + dx + C::HX * (dy + C::HY * dz);
+                    double un[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) un[v] = tile[v][o];
+                    nb_ok = nb_ok && admissible<D>(un, gam);
+                    rmax = fmax(rmax, un[0]);
+                    rmin = fmin(rmin, un[0]);
+                    pmin = fmin(pmin, pressure<D>(un, gam));
+                }
+        if (!nb_ok && active) *err = ERR_NONPHYSICAL;
+        rmax *= 1.0 + lim.kappa;
+        rmin *= 1.0 - lim.kappa;
+        pmin *= 1.0 - lim.kappa;
+        PhiInv<D> pi;
+        pi.init(ref, gam);
+        if (active && ok) {
+            // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
+#pragma unroll 1
+            for (int tau = hf; tau < NPTS; tau += 2) {
+                const double rs = ref[0] + (double)inc[((long)tau * NV + 0) * g.ncell + cell];
+                if (rs < rmin) th_rho = fmin(th_rho, (ref[0] - rmin) / (ref[0] - rs));
+                else if (rs > rmax) th_rho = fmin(th_rho, (rmax - ref[0]) / (rs - ref[0]));
+            }
+        }
+        th_rho = fmin(th_rho, __shfl_xor(th_rho, 32, 64));
+        if (active && ok) {
+#pragma unroll 1
+            for (int tau = hf; tau < NPTS; tau += 2) {
+                double w[NV], d[NV], u[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)tau * NV + v) * g.ncell + cell];
+                pi.apply(w, d);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
+                if (pressure<D>(u, gam) >= pmin) continue;
+                double lo = 0.0, hi = 1.0;
+#pragma unroll 1
+                for (int it = 0; it < 60; ++it) {
+                    const double m = 0.5 * (lo + hi);
+                    double um[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) um[v] = ref[v] + m * th_rho * d[v];
+                    if (pressure<D>(um, gam) >= pmin) lo = m; else hi = m;
+                }
+                th_p = fmin(th_p, lo);
+            }
+        }
+        th_p = fmin(th_p, __shfl_xor(th_p, 32, 64));
+    }
+    if (active && hf == 0) {
+        theta[cell] = th_rho;
+        theta[g.ncell + cell] = th_p;
+    }
+}
+
+// ------------------------------------------------------------------- flux ---
+template <int D, int R, int A>
+__device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__ U, const float *__restrict__ inc,
+                                                      const double *__restrict__ theta, const Geom &g, long cell,
+                                                      long lower, int hll, double *Fbar)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NG = S::NG;
+    double refL[NV], refR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { refL[v] = U[v * g.ncell + lower]; refR[v] = U[v * g.ncell + cell]; }
+    const double thL = theta[lower] * theta[g.ncell + lower];
+    const double thR = theta[cell] * theta[g.ncell + cell];
+    PhiInv<D> piL, piR;
+    piL.init(refL, g.gamma);
+    piR.init(refR, g.gamma);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
+#pragma unroll 1
+    for (int gi = 0; gi < NG; ++gi) {
+        double wL[NV], wR[NV], dL[NV], dR[NV], uL[NV], uR[NV], F[NV];
+        const int sL = (2 * A + 1) * NG + gi, sR = (2 * A + 0) * NG + gi;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            wL[v] = (double)inc[((long)sL * NV + v) * g.ncell + lower];
+            wR[v] = (double)inc[((long)sR * NV + v) * g.ncell + cell];
+        }
+        piL.apply(wL, dL);
+        piR.apply(wR, dR);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { uL[v] = refL[v] + thL * dL[v]; uR[v] = refR[v] + thR * dR[v]; }
+        riemann<D, A>(uL, uR, g.gamma, hll, F);
+        const double w = face_weight<D, R>(gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[v] += w * F[v];
+    }
+}
+
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_flux_mixed(const double *__restrict__ U, const float *__restrict__ inc,
+                                                    const double *__restrict__ theta, double *__restrict__ fbar,
+                                                    int *__restrict__ err, Geom g, int hll)
+{
+    constexpr int NV = D + 2;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
+    const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
+    double F[NV];
+    bool ok = true;
+    {
+        const long lower = wrapi(cx - 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
+        lower_face_flux_mixed<D, R, 0>(U, inc, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(0 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    {
+        const long lower = cx + (long)g.n[0] * (wrapi(cy - 1, g.n[1]) + (long)g.n[1] * cz);
+        lower_face_flux_mixed<D, R, 1>(U, inc, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(1 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    if constexpr (D == 3) {
+        const long lower = cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz - 1, g.n[2]));
+        lower_face_flux_mixed<D, R, 2>(U, inc, theta, g, cell, lower, hll, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar[(2 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    if (!ok) *err = ERR_NONPHYSICAL;
+}
+
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_states_mixed(const double *__restrict__ U, const float *__restrict__ inc,
+                                                      const double *__restrict__ theta, double *__restrict__ states,
+                                                      Geom g)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NPTS = S::NPTS;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = U[v * g.ncell + cell];
+    const double th = theta[cell] * theta[g.ncell + cell];
+    PhiInv<D> pi;
+    pi.init(ref, g.gamma);
+#pragma unroll 1
+    for (int s = 0; s < NPTS; ++s) {
+        double w[NV], d[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)s * NV + v) * g.ncell + cell];
+        pi.apply(w, d);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) states[(cell * NPTS + s) * NV + v] = ref[v] + th * d[v];
+    }
+}
+
+template <int D, int R, bool BF>
+hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Limiter &lim, int riemann,
+                      const double *U0, const double *Uin, double *out, int stage, double dt, double *states,
+                      hipStream_t s, const Timing &tm)
+{
+    using C = Cfg<D, R>;
+    using M = MixCfg<D, R>;
+    auto mark = [&](int kind, int begin) { if (tm.on) tm.record(tm.self, kind, s, begin); };
+    const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
+                      (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
+    const long grid = ((nblk + 7) / 8) * 8;
+    mark(KT_RECON, 1);
+    hipLaunchKernelGGL((k_recon_mixed<D, R, BF>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full, t.lin,
+                       w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw);
+    mark(KT_RECON, 0);
+    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
+    if (states) {
+        hipLaunchKernelGGL((k_states_mixed<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.inc32, w.theta, states, g);
+        return hipGetLastError();
+    }
+    mark(KT_FLUX, 1);
+    hipLaunchKernelGGL((k_flux_mixed<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.inc32, w.theta, w.fbar, w.err, g,
+                       riemann);
+    mark(KT_FLUX, 0);
+    mark(KT_UPDATE, 1);
+    hipError_t e = launch_update(D, g, w, U0, Uin, out, stage, dt, s);
+    mark(KT_UPDATE, 0);
+    return e;
+}
+
+}  // namespace
+
+bool mixed_supported(int dim, int R) { return !(dim == 3 && R == 3); }
+
+int mixed_operand_slots(int dim, int R, int which)
+{
+#define KF_SLOTS(d, r) return which == 0 ? MixCfg<d, r>::A_FULL : MixCfg<d, r>::A_LIN
+    if (dim == 2 && R == 2) KF_SLOTS(2, 2);
+    if (dim == 2 && R == 3) KF_SLOTS(2, 3);
+    if (dim == 3 && R == 2) KF_SLOTS(3, 2);
+#undef KF_SLOTS
+    return -1;
+}
+
+hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixTables &t, const Work &w,
+                            const Limiter &lim, int riemann, const double *U0, const double *Uin, double *out,
+                            int stage, double dt, double *states, hipStream_t s, const Timing &tm)
+{
+#define KF_MIX(d, r)                                                                                              \
+    return bf16 ? mixed_impl<d, r, true>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm)       \
+                : mixed_impl<d, r, false>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm)
+    if (dim == 2 && R == 2) KF_MIX(2, 2);
+    if (dim == 2 && R == 3) KF_MIX(2, 3);
+    if (dim == 3 && R == 2) KF_MIX(3, 2);
+#undef KF_MIX
+    return hipErrorInvalidValue;
+}
+
+}  // namespace kfvm

@@ -21,7 +21,7 @@ EXPORTED = [
     "kfvm_init", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream", "kfvm_set_precision",
     "kfvm_set_limiter", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
-    "kfvm_set_timing", "kfvm_kernel_times",
+    "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags",
 ]
 KERNEL_CLASSES = ("recon", "flux", "update")
 
@@ -77,6 +77,7 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_weights_size": ([ip, ip], ip),
         "kfvm_last_error": ([vp], C.c_char_p),
         "kfvm_set_timing": ([vp, ip], ip),
+        "kfvm_set_flags": ([vp, vp], ip),
         "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
         "kfvm_destroy": ([vp], None),
     }
@@ -223,6 +224,18 @@ class KFVM:
 
     def status(self):
         return self.lib.kfvm_status(self._h)
+
+    def set_flags(self, flags):
+        """flags: uint8 CUDA tensor [nvar, ncell] (1 = WENO-AO, 0 = linear S0) or None."""
+        if flags is None:
+            self._flags = None
+            self._check(self.lib.kfvm_set_flags(self._h, None))
+            return
+        if not (flags.is_cuda and flags.dtype == torch.uint8 and flags.is_contiguous()
+                and flags.numel() == self.nvar * (self.shape[1] * self.shape[2] * (self.shape[3] if self.dim == 3 else 1))):
+            raise ValueError("flags must be a contiguous uint8 CUDA tensor of nvar * ncell entries")
+        self._flags = flags
+        self._check(self.lib.kfvm_set_flags(self._h, C.c_void_p(flags.data_ptr())))
 
     def set_timing(self, on: bool):
         self._check(self.lib.kfvm_set_timing(self._h, int(on)))
