@@ -62,20 +62,25 @@ __device__ __forceinline__ f16v mfma(uint4 a, uint4 b, f16v c)
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
 }
 
-// hi/lo split of a scaled increment into two 16-bit values (bit patterns)
+// hi/lo split of two scaled increments into packed 16-bit pairs: hi rounds to
+// nearest, the residual y - hi is exact in float32 and is rounded the same way,
+// so hi + lo keeps ~22 (fp16) or ~16 (bf16) significant bits of y.
 template <bool BF>
-__device__ __forceinline__ void split16(double y, uint16_t &hi, uint16_t &lo)
+__device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uint32_t &lo)
 {
+    // keep the float32 rounding step: without it the compiler folds the two
+    // truncations into one software-emulated float64 -> half conversion
+    asm volatile("" : "+v"(ya), "+v"(yb));
     if constexpr (BF) {
-        const __bf16 h = (__bf16)(float)y;
-        const __bf16 l = (__bf16)(float)(y - (double)(float)h);
-        hi = __builtin_bit_cast(uint16_t, h);
-        lo = __builtin_bit_cast(uint16_t, l);
+        const __bf16 ha = (__bf16)ya, hb = (__bf16)yb;
+        const __bf16 la = (__bf16)(ya - (float)ha), lb = (__bf16)(yb - (float)hb);
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
+        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | (uint32_t)__builtin_bit_cast(uint16_t, lb) << 16;
     } else {
-        const _Float16 h = (_Float16)(float)y;
-        const _Float16 l = (_Float16)(float)(y - (double)(float)h);
-        hi = __builtin_bit_cast(uint16_t, h);
-        lo = __builtin_bit_cast(uint16_t, l);
+        const _Float16 ha = (_Float16)ya, hb = (_Float16)yb;
+        const _Float16 la = (_Float16)(ya - (float)ha), lb = (_Float16)(yb - (float)hb);
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
+        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | (uint32_t)__builtin_bit_cast(uint16_t, lb) << 16;
     }
 }
 
@@ -124,23 +129,24 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
     int ex = 0;
     if (amax > 0.0) frexp(amax, &ex);          // amax in [2^(ex-1), 2^ex)
     const int e = ex - 1;
-    const double sc = ldexp(1.0, SB - e), unscale = ldexp(1.0, e - SB - sw);
+    const double sc = ldexp(1.0, SB - e);
+    const int ue = e - SB - sw;                    // accumulator units: value = acc * 2^ue
     uint4 bh[KS], bl[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        uint16_t h[8], l[8];
+        uint32_t h[4], l[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) split16<BF>(dl[ks][i] * sc, h[i], l[i]);
-        bh[ks] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16, h[4] | (uint32_t)h[5] << 16,
-                            h[6] | (uint32_t)h[7] << 16);
-        bl[ks] = make_uint4(l[0] | (uint32_t)l[1] << 16, l[2] | (uint32_t)l[3] << 16, l[4] | (uint32_t)l[5] << 16,
-                            l[6] | (uint32_t)l[7] << 16);
+        for (int i = 0; i < 4; ++i)
+            split_pair<BF>((float)(dl[ks][2 * i] * sc), (float)(dl[ks][2 * i + 1] * sc), h[i], l[i]);
+        bh[ks] = make_uint4(h[0], h[1], h[2], h[3]);
+        bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
     const bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
     if (__any(use_weno && active)) {
-        // smoothness indicators: lane-local sums over its four stencils, then the partner's four
-        double bp[4] = {0.0, 0.0, 0.0, 0.0};
+        // smoothness indicators: float32 sums of squares over this lane's four
+        // stencils (q = 4 hf + i), in accumulator units squared
+        float bp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = M::TD_BEGIN; t < M::NTF; ++t) {
             f16v acc = {};
@@ -155,44 +161,33 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int tau = 4 * t + j / 4;
-                if (tau >= NPTS && tau < NROWS) {
-                    const double dv = (double)acc[j] * unscale;
-                    bp[j % 4] += dv * dv;
-                }
+                if (tau >= NPTS && tau < NROWS) bp[j % 4] += acc[j] * acc[j];
             }
         }
-        double beta[8];
+        // nonlinear weights (eq. nlinWts) of this lane's four stencils in FP64;
+        // the normalising sum and omega_0 come from the partner half-wave
+        double om[4], part = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double other = __shfl_xor(bp[i], 32, 64);
-            beta[i] = hf ? other : bp[i];
-            beta[4 + i] = hf ? bp[i] : other;
+            const int q = 4 * hf + i;
+            const double beta = ldexp((double)bp[i], 2 * ue);
+            om[i] = q < NST ? lin_w<D>(q) / (beta * beta + EPS_WENO) : 0.0;
+            part += om[i];
         }
-        // nonlinear weights (eq. nlinWts) and WENO-AO coefficients (eq. wenoAOrec) in FP64
-        double c[8];
+        const double inv = 1.0 / (part + __shfl_xor(part, 32, 64));
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = q == 0 ? 1.0 : 0.0;
-        if (use_weno) {
-            double om[NST], sum = 0.0;
-#pragma unroll
-            for (int q = 0; q < NST; ++q) {
-                om[q] = lin_w<D>(q) / (beta[q] * beta[q] + EPS_WENO);
-                sum += om[q];
-            }
-#pragma unroll
-            for (int q = 0; q < NST; ++q) om[q] /= sum;
-            c[0] = om[0] / lin_w<D>(0);
-#pragma unroll
-            for (int q = 1; q < NST; ++q) c[q] = om[q] - om[0] * lin_w<D>(q) / lin_w<D>(0);
-        }
-        // this half-wave's four coefficients, selected as values (a select of two
-        // array elements would otherwise become a dynamically indexed private array)
-        double cm[4];
+        for (int i = 0; i < 4; ++i) om[i] *= inv;
+        const double other0 = __shfl_xor(om[0], 32, 64);     // every lane takes part in the exchange
+        const double om0 = hf ? other0 : om[0];
+        // WENO-AO coefficients (eq. wenoAOrec) of this lane's stencils, or the
+        // linear S0 value for a cell the gate marks smooth
+        float cm[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            double a = c[i], b = c[4 + i];
-            asm volatile("" : "+v"(a), "+v"(b));
-            cm[i] = hf ? b : a;
+            const int q = 4 * hf + i;
+            double cq = q == 0 ? om0 / lin_w<D>(0) : (q < NST ? om[i] - om0 * lin_w<D>(q) / lin_w<D>(0) : 0.0);
+            if (!use_weno) cq = q == 0 ? 1.0 : 0.0;
+            cm[i] = (float)cq;
         }
         // blended face-point increments
 #pragma unroll
@@ -210,12 +205,11 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
             for (int gq = 0; gq < 4; ++gq) {
                 const int tau = 4 * t + gq;
                 if (tau < NPTS) {
-                    double part = 0.0;
+                    float part4 = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) part += cm[i] * (double)acc[4 * gq + i];
-                    part *= unscale;
-                    const double tot = part + __shfl_xor(part, 32, 64);
-                    if ((tau & 1) == hf && active) inc[((long)tau * NV + K) * ncell + cell] = (float)tot;
+                    for (int i = 0; i < 4; ++i) part4 += cm[i] * acc[4 * gq + i];
+                    const float tot = part4 + __shfl_xor(part4, 32, 64);
+                    if ((tau & 1) == hf && active) inc[((long)tau * NV + K) * ncell + cell] = ldexpf(tot, ue);
                 }
             }
         }
@@ -237,12 +231,12 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
                 const int tau = 32 * t + 8 * (j / 4) + 4 * hf + j % 4;
                 // this lane owns tau; keep the ownership rule (tau & 1) == hf of the
                 // blended path by exchanging with the partner
-                const double v = (double)acc[j] * unscale;
-                const double other = __shfl_xor(v, 32, 64);
+                const float v = ldexpf(acc[j], ue);
+                const float other = __shfl_xor(v, 32, 64);
                 const int tau_o = 32 * t + 8 * (j / 4) + 4 * (1 - hf) + j % 4;
                 if (active) {
-                    if (tau < NPTS && (tau & 1) == hf) inc[((long)tau * NV + K) * ncell + cell] = (float)v;
-                    if (tau_o < NPTS && (tau_o & 1) == hf) inc[((long)tau_o * NV + K) * ncell + cell] = (float)other;
+                    if (tau < NPTS && (tau & 1) == hf) inc[((long)tau * NV + K) * ncell + cell] = v;
+                    if (tau_o < NPTS && (tau_o & 1) == hf) inc[((long)tau_o * NV + K) * ncell + cell] = other;
                 }
             }
         }
