@@ -165,6 +165,47 @@ int kfvm_weights_size(int dim, int R);
  * array must stay valid while work that reads it is queued. */
 int kfvm_set_flags(kfvm_ctx *ctx, const uint8_t *flags);
 
+/* ---- learned troubled-cell gate -------------------------------------------
+ * A small network decides per (variable, cell) whether the WENO-AO machinery
+ * (substencils, smoothness indicators, nonlinear weights; section 3.2-3.3) is
+ * needed or the linear full-stencil value suffices, in place of the paper's
+ * KXRCF indicator (section 3.5).  Network: n_in -> 32 -> 32 -> 1 logit, GELU
+ * (tanh form) after both hidden layers; n_in = 25 in 2D (the 5 x 5 window of the
+ * variable around the cell, offsets lexicographic with x slowest) and 33 in 3D
+ * (the radius-2 sphere S0 in its stencil order).  Inputs: increments W_h - W_c
+ * of the linearised primitive variable divided by 2^ex, where max|W_h - W_c| lies
+ * in [2^(ex-1), 2^ex).  Parameters: one float32 vector W1[32][n_in], b1[32],
+ * W2[32][32], b2[32], w3[32], b3.  Inference runs the hidden layers on BF16
+ * matrix cores with float32 accumulation (inputs, W1, W2 and the first hidden
+ * activations rounded to BF16); training keeps float32 masters. */
+
+/* Sizes of the gate network for dim (host only). */
+int kfvm_mlp_sizes(int dim, int *n_in, int *n_params);
+
+/* Enable the gate in the split-precision path: params is a device float32
+ * vector (copied), a (variable, cell) takes WENO-AO when its logit exceeds
+ * threshold.  params == NULL disables it.  Clears kfvm_set_flags. */
+int kfvm_set_gate(kfvm_ctx *ctx, const float *params, float threshold);
+
+/* Copy the gate's decisions of the last reconstruction, flags[nvar][ncells]
+ * bytes (1 = WENO-AO), to a device buffer (asynchronous). */
+int kfvm_get_flags(kfvm_ctx *ctx, uint8_t *flags);
+
+/* Training samples from state U: x[nvar][ncells][n_in] float32 gate inputs and
+ * ratio[nvar][ncells] float32 = omega_0 / gamma_0 of the FP64 WENO-AO
+ * reconstruction (eq. nlinWts; 1 where the variable is linear).  Device buffers. */
+int kfvm_gate_samples(kfvm_ctx *ctx, const double *U, float *x, float *ratio);
+
+/* One training step on a batch of B samples x[B][n_in], labels y[B] in {0, 1}
+ * (device buffers): mean loss pos_weight y softplus(-z) + (1 - y) softplus(z) of
+ * the logit z, its gradient (straight through the BF16 roundings), reduced in
+ * a fixed order, and, if lr > 0, one Adam step (beta 0.9, 0.999, eps 1e-8, bias
+ * corrected at step t >= 1) on params with moments adam_m, adam_v.  loss (one
+ * float), grad (n_params) and logits (B) are optional outputs; y may be NULL
+ * when lr == 0. */
+int kfvm_mlp_train_step(kfvm_ctx *ctx, const float *x, const float *y, int B, float *params, float *adam_m,
+                        float *adam_v, int t, float lr, float pos_weight, float *loss, float *grad, float *logits);
+
 /* on != 0: bracket every subsequent kernel launch with HIP events on the
  * context's stream (adds a few microseconds per launch). */
 int kfvm_set_timing(kfvm_ctx *ctx, int on);

@@ -68,6 +68,8 @@ def _load():
         _lib.oracle_riemann.argtypes = [P(_Ctx), C.c_long, P(C.c_double), P(C.c_double), C.c_int,
                                         P(C.c_double)]
         _lib.oracle_riemann.restype = None
+        _lib.oracle_omega_ratio.argtypes = [P(_Ctx), P(C.c_double), P(C.c_float)]
+        _lib.oracle_omega_ratio.restype = C.c_int
         _lib.oracle_phi.argtypes = [P(_Ctx), P(C.c_double), P(C.c_double), P(C.c_double)]
         _lib.oracle_phi.restype = None
     return _lib
@@ -199,3 +201,42 @@ class Oracle:
         B = np.empty((self.nvar, self.nvar))
         self._lib.oracle_phi(C.byref(self._ctx), _ptr(ref), _ptr(A), _ptr(B))
         return A, B
+
+    def omega_ratio(self, U):
+        """omega_0 / gamma_0 of the WENO-AO weights per (variable, cell): [nvar, cells] float32."""
+        U = self._check_U(U)
+        out = np.empty((self.nvar, self.ncell), dtype=np.float32)
+        self._call(self._lib.oracle_omega_ratio(C.byref(self._ctx), _ptr(U), _ptr(out, C.c_float)))
+        return out
+
+    def gate_inputs(self, U):
+        """Gate-network inputs of every (variable, cell): [nvar, cells, n_in] float64.
+        2D: the 5 x 5 window (offsets lexicographic, x slowest); 3D: the radius-2
+        sphere in S0 order.  W = Phi(U_cell) U_h, increments W_h - W_c divided by the
+        power of two 2^ex with max |W_h - W_c| in [2^(ex-1), 2^ex)."""
+        U = self._check_U(U)
+        d, nv = self.d, self.nvar
+        if d == 2:
+            offs = [(i - 2, j - 2) for i in range(5) for j in range(5)]
+        else:
+            offs = [tuple(o) for o in _w.full_stencil(3, 2)]
+        n = self.shape[::-1]
+        cells = np.arange(self.ncell)
+        idx = [cells % n[0], (cells // n[0]) % n[1]] + ([cells // (n[0] * n[1])] if d == 3 else [])
+        flat = U.reshape(nv, -1)
+        out = np.empty((nv, self.ncell, len(offs)))
+        Phi = np.empty((self.ncell, nv, nv))
+        for c in range(self.ncell):
+            Phi[c] = self.phi(flat[:, c])[0]
+        Wc = np.einsum("cij,jc->ci", Phi, flat)
+        for h, o in enumerate(offs):
+            nb = np.zeros(self.ncell, dtype=np.int64)
+            stride = 1
+            for a in range(d):
+                nb += ((idx[a] + o[a]) % n[a]) * stride
+                stride *= n[a]
+            W = np.einsum("cij,jc->ci", Phi, flat[:, nb])
+            out[:, :, h] = (W - Wc).T
+        amax = np.abs(out).max(axis=2, keepdims=True)
+        ex = np.where(amax > 0, np.frexp(np.where(amax > 0, amax, 1.0))[1], 0)
+        return np.ldexp(out, -ex)

@@ -146,7 +146,15 @@ static void matvec(int nv, const double *A, const double *x, double *y)
 
 /* --------------------------------------------- Riemann states of one cell --- */
 /* states: [n_pts][nvar].  Returns OK or ERR_NONPHYSICAL. */
+static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio);
+
 static int cell_states(const oracle_ctx *c, const double *U, long cell, double *states)
+{
+    return cell_states_ex(c, U, cell, states, NULL);
+}
+
+/* ratio (optional): omega_0 / gamma_0 per variable, 1 where the variable is linear */
+static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio)
 {
     int nv = c->nvar, n0 = c->n0, np = c->n_pts, nd = c->n_der;
     long N = ncells(c);
@@ -190,6 +198,7 @@ static int cell_states(const oracle_ctx *c, const double *U, long cell, double *
         if (c->flags) use_weno = c->flags[(long)k * N + cell] != 0;
         if (!use_weno) {
             for (int s = 0; s < np; ++s) wpt[s * nv + k] = vals[0 * np + s];
+            if (ratio) ratio[k] = 1.0f;
             continue;
         }
         /* nonlinear weights (eq. nlinWts) */
@@ -199,6 +208,7 @@ static int cell_states(const oracle_ctx *c, const double *U, long cell, double *
             sum += om[q];
         }
         for (int q = 0; q < c->nst; ++q) om[q] /= sum;
+        if (ratio) ratio[k] = (float)(om[0] / c->lin_w[0]);
         /* WENO-AO blend (eq. wenoAOrec) */
         for (int s = 0; s < np; ++s) {
             double f = om[0] / c->lin_w[0] * vals[0 * np + s];
@@ -480,6 +490,26 @@ void oracle_riemann(const oracle_ctx *c, long count, const double *uL, const dou
 {
     for (long i = 0; i < count; ++i)
         riemann(c, uL + i * c->nvar, uR + i * c->nvar, axis, F + i * c->nvar);
+}
+
+/* omega_0 / gamma_0 of every (variable, cell): out[nvar][cells] (the gate's label source). */
+int oracle_omega_ratio(const oracle_ctx *c, const double *U, float *out)
+{
+    long N = ncells(c);
+    int nv = c->nvar, err = OK;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long cell = 0; cell < N; ++cell) {
+        double *st = (double *)malloc(sizeof(double) * c->n_pts * nv);
+        float r[MAXV];
+        int e = cell_states_ex(c, U, cell, st, r);
+        if (e != OK) {
+#pragma omp atomic write
+            err = e;
+        }
+        for (int k = 0; k < nv; ++k) out[k * N + cell] = r[k];
+        free(st);
+    }
+    return err;
 }
 
 /* Phi and Phi^-1 at a reference state, for unit tests. */

@@ -33,6 +33,15 @@ struct kfvm_ctx {
     std::vector<double> host_tables;
     uint4 *d_mix_full = nullptr, *d_mix_lin = nullptr;
     int mix_sw = 0, mix_mode = -1;
+    // learned gate (fused into the split-precision reconstruction)
+    uint4 *d_gate_w = nullptr;
+    float *d_gate_vec = nullptr;
+    uint8_t *d_flags_out = nullptr;
+    float gate_thr = 0.f;
+    int gate_on = 0;
+    // gate-network training workspace
+    float *d_mlp_ws = nullptr;
+    size_t mlp_ws_floats = 0;
 };
 
 namespace {
@@ -308,6 +317,11 @@ static void record_event(void *self, int kind, hipStream_t s, int begin)
 
 static kfvm::Timing timing_of(kfvm_ctx *c) { return kfvm::Timing{c->timing, record_event, c}; }
 
+static kfvm::GateArgs gate_of(kfvm_ctx *c)
+{
+    return kfvm::GateArgs{c->gate_on ? c->d_gate_w : nullptr, c->d_gate_vec, c->gate_thr, c->d_flags_out};
+}
+
 static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
 {
     hipError_t e;
@@ -318,7 +332,7 @@ static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *
     } else {
         kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
         e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
-                                   c->riemann, U0, Uin, out, stage, dt, nullptr, c->stream, timing_of(c));
+                                   c->riemann, U0, Uin, out, stage, dt, nullptr, c->stream, timing_of(c), gate_of(c));
     }
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return KFVM_OK;
@@ -435,7 +449,8 @@ int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
     } else {
         kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
         e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
-                                   c->riemann, U, U, nullptr, 0, 0.0, states, c->stream, kfvm::Timing{0, nullptr, nullptr});
+                                   c->riemann, U, U, nullptr, 0, 0.0, states, c->stream, kfvm::Timing{0, nullptr, nullptr},
+                                   gate_of(c));
     }
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return c->checking ? sync_check(c) : KFVM_OK;
@@ -445,6 +460,108 @@ int kfvm_set_flags(kfvm_ctx *c, const uint8_t *flags)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     c->work.flags_in = flags;
+    if (flags) c->gate_on = 0;
+    return KFVM_OK;
+}
+
+int kfvm_mlp_sizes(int dim, int *n_in, int *n_params)
+{
+    if ((dim != 2 && dim != 3) || !n_in || !n_params) return KFVM_ERR_ARG;
+    *n_in = kfvm::mlp_n_in(dim);
+    *n_params = kfvm::mlp_n_params(dim);
+    return KFVM_OK;
+}
+
+int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!params) {
+        c->gate_on = 0;
+        return KFVM_OK;
+    }
+    if (!kfvm::mixed_supported(c->dim, c->R)) return fail(c, KFVM_ERR_ARG, "the gate needs the split-precision path");
+    const int nin = kfvm::mlp_n_in(c->dim), P = kfvm::mlp_n_params(c->dim), H = 32;
+    std::vector<float> p(P);
+    HIP_TRY(c, hipMemcpy(p.data(), params, sizeof(float) * P, hipMemcpyDeviceToHost));
+    const int ksg = (nin + 15) / 16, slots = kfvm::gate_operand_slots(c->dim);
+    std::vector<uint16_t> w((size_t)slots * 8, 0);
+    // W1 as the A operand of k-step ks: lane l holds W1[l % 32][16 ks + 8 (l / 32) + i]
+    for (int ks = 0; ks < ksg; ++ks)
+        for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 8; ++i) {
+                const int m = l % 32, k = 16 * ks + 8 * (l / 32) + i;
+                w[((size_t)ks * 64 + l) * 8 + i] = k < nin ? to_bf16(p[m * nin + k]) : 0;
+            }
+    const float *W2 = p.data() + H * nin + H;
+    for (int ks = 0; ks < 2; ++ks)
+        for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 8; ++i) {
+                const int m = l % 32, k = 16 * ks + 8 * (l / 32) + i;
+                w[((size_t)(ksg + ks) * 64 + l) * 8 + i] = to_bf16(W2[m * H + k]);
+            }
+    std::vector<float> vec(97);
+    for (int m = 0; m < H; ++m) {
+        vec[m] = p[H * nin + m];                       // b1
+        vec[32 + m] = p[H * nin + H + H * H + m];      // b2
+        vec[64 + m] = p[H * nin + H + H * H + H + m];  // w3
+    }
+    vec[96] = p[P - 1];                                 // b3
+    if (!c->d_gate_w) {
+        int rc = alloc(c, (void **)&c->d_gate_w, w.size() * 2);
+        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_gate_vec, sizeof(float) * 97);
+        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_flags_out, (size_t)c->nvar * c->geom.ncell);
+        if (rc != KFVM_OK) return rc;
+    }
+    HIP_TRY(c, hipMemcpy(c->d_gate_w, w.data(), w.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_gate_vec, vec.data(), sizeof(float) * 97, hipMemcpyHostToDevice));
+    c->gate_thr = threshold;
+    c->gate_on = 1;
+    c->work.flags_in = nullptr;
+    return KFVM_OK;
+}
+
+int kfvm_get_flags(kfvm_ctx *c, uint8_t *flags)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!flags) return fail(c, KFVM_ERR_ARG, "null buffer");
+    if (!c->d_flags_out) return fail(c, KFVM_ERR_STATE, "no gate has run");
+    HIP_TRY(c, hipMemcpyAsync(flags, c->d_flags_out, (size_t)c->nvar * c->geom.ncell, hipMemcpyDeviceToDevice,
+                              c->stream));
+    return KFVM_OK;
+}
+
+int kfvm_gate_samples(kfvm_ctx *c, const double *U, float *x, float *ratio)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !x || !ratio) return fail(c, KFVM_ERR_ARG, "null buffer");
+    hipError_t e = kfvm::launch_gate_inputs(c->dim, c->geom, U, x, c->stream);
+    kfvm::Tables t{c->d_tables};
+    if (e == hipSuccess) e = kfvm::launch_recon_ratio(c->dim, c->R, c->geom, t, c->work, c->lim, U, ratio, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    return c->checking ? sync_check(c) : KFVM_OK;
+}
+
+int kfvm_mlp_train_step(kfvm_ctx *c, const float *x, const float *y, int B, float *params, float *adam_m,
+                        float *adam_v, int t, float lr, float pos_weight, float *loss, float *grad, float *logits)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!x || !params || B <= 0) return fail(c, KFVM_ERR_ARG, "null buffer or empty batch");
+    if (lr > 0.f && (!adam_m || !adam_v || !y || t < 1)) return fail(c, KFVM_ERR_ARG, "an update needs y, m, v, t >= 1");
+    const size_t need = kfvm::mlp_workspace_floats(c->dim, B);
+    if (need > c->mlp_ws_floats) {
+        if (c->d_mlp_ws) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            hipFree(c->d_mlp_ws);
+            for (auto &p : c->allocs)
+                if (p == c->d_mlp_ws) p = nullptr;
+        }
+        int rc = alloc(c, (void **)&c->d_mlp_ws, need * sizeof(float));
+        if (rc != KFVM_OK) return rc;
+        c->mlp_ws_floats = need;
+    }
+    hipError_t e = kfvm::launch_mlp_train(c->dim, x, y, B, params, adam_m, adam_v, t, lr, pos_weight, loss, grad,
+                                          logits, c->d_mlp_ws, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
     return KFVM_OK;
 }
 
@@ -484,7 +601,8 @@ void kfvm_destroy(kfvm_ctx *c)
     if (!c) return;
     hipStreamSynchronize(c->stream);
     for (auto &e : c->events) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
-    for (void *p : c->allocs) hipFree(p);
+    for (void *p : c->allocs)
+        if (p) hipFree(p);
     delete c;
 }
 

@@ -149,6 +149,25 @@ struct PhiRows {
         e0 = (gam - 1.0) * uu / 2.0;
         e_e = gam - 1.0;
     }
+    // component k (runtime) of Phi u, same summation order as w_component
+    __device__ __forceinline__ double row(int k, const double *u) const
+    {
+        if (k == 0) return u[0];
+        if (k == D + 1) {
+            double s = e0 * u[0];
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += e_mom[a] * u[1 + a];
+            return s + e_e * u[D + 1];
+        }
+        double mv = 0.0, ua = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            mv = (k == 1 + a) ? m_vel[a] : mv;
+            ua = (k == 1 + a) ? u[1 + a] : ua;
+        }
+        const double s = mv * u[0];
+        return s + inv_rho * ua;
+    }
 };
 
 // Component K of W = Phi U at LDS index o, summed in the column order of the
@@ -257,6 +276,23 @@ __device__ __forceinline__ double face_weight(int gi)
     return w;
 }
 
+
+// GELU, tanh form (Hendrycks & Gimpel 2016), float32, with
+// tanh(a) = 1 - 2 / (1 + exp(2a)) on the hardware exponential
+__device__ __forceinline__ float gelu_f(float z)
+{
+    const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __expf(2.f * a));
+    return 0.5f * z * (1.f + t);
+}
+
+__device__ __forceinline__ float gelu_grad_f(float z)
+{
+    const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __expf(2.f * a));
+    const float da = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
+    return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * da;
+}
 
 }  // namespace dev
 }  // namespace kfvm

@@ -59,14 +59,37 @@ hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const
                            hipStream_t s, const Timing &tm);
 hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0, const double *Uin, double *out,
                          int stage, double dt, hipStream_t s);
+// Learned troubled-cell gate fused into the split-precision reconstruction
+// (w == nullptr: no gate).  w: BF16 operand slots of W1 and W2 (8 values per lane
+// and slot, see rhs_mixed.hip); vec: b1[32], b2[32], w3[32], b3.
+struct GateArgs {
+    const uint4 *w;
+    const float *vec;
+    float thr;
+    uint8_t *flags_out;   // [nvar][ncell] decisions of the last evaluation (1 = WENO-AO)
+};
+
 bool mixed_supported(int dim, int R);
+int gate_operand_slots(int dim);
 int mixed_operand_slots(int dim, int R, int which);   // which: 0 full, 1 lin; 16-byte slots
 hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixTables &t, const Work &w,
                             const Limiter &lim, int riemann, const double *U0, const double *Uin, double *out,
-                            int stage, double dt, double *states, hipStream_t s, const Timing &tm);
+                            int stage, double dt, double *states, hipStream_t s, const Timing &tm,
+                            const GateArgs &ga);
 hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s);
+
+// gate network: training and sample export (mlp.hip)
+int mlp_n_in(int dim);
+int mlp_n_params(int dim);
+size_t mlp_workspace_floats(int dim, int B);
+hipError_t launch_gate_inputs(int dim, const Geom &g, const double *U, float *x, hipStream_t s);
+hipError_t launch_mlp_train(int dim, const float *x, const float *y, int B, float *prm, float *m, float *v, int t,
+                            float lr, float pos_weight, float *loss, float *grad, float *logits, float *ws,
+                            hipStream_t s);
+hipError_t launch_recon_ratio(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                              const double *U, float *ratio, hipStream_t s);
 
 }  // namespace kfvm

@@ -32,7 +32,7 @@ using namespace dev;
 template <int D, int R, int K>
 __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
                                           const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                          double *__restrict__ face, long cell, long ncell)
+                                          double *__restrict__ face, long cell, long ncell, float *__restrict__ ratio)
 {
     using C = Cfg<D, R>;
     using S = typename C::S;
@@ -81,6 +81,7 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
 #pragma unroll
         for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_w<D>(q) / lin_w<D>(0);
     }
+    if (ratio) ratio[(long)K * ncell + cell] = (float)cq[0];   // omega_0 / gamma_0 (1 when linear)
 #pragma unroll 1
     for (int s = 0; s < NPTS; ++s) {
         double v[NST];
@@ -108,13 +109,13 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
 template <int D, int R, int... K>
 __device__ __forceinline__ void recon_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
                                                const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                               double *__restrict__ face, long cell, long ncell,
+                                               double *__restrict__ face, long cell, long ncell, float *ratio,
                                                std::integer_sequence<int, K...>)
 {
     // one pass per variable; the empty asm keeps each pass's LDS reads from
     // being hoisted into a single register-hungry prologue
     ((recon_var<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wt, ph, flags, face,
-                         cell, ncell)),
+                         cell, ncell, ratio)),
      ...);
 }
 
@@ -122,7 +123,7 @@ template <int D, int R>
 __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restrict__ U, const double *__restrict__ wt,
                                                          double *__restrict__ face, double *__restrict__ theta,
                                                          int *__restrict__ err, const uint8_t *__restrict__ flags,
-                                                         Geom g, Limiter lim)
+                                                         Geom g, Limiter lim, float *__restrict__ ratio)
 {
     using C = Cfg<D, R>;
     using S = typename C::S;
@@ -171,7 +172,7 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     // entries, applied row by row with one compile-time pass per variable
     PhiRows<D> ph;
     ph.init(ref, gam);
-    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, std::make_integer_sequence<int, NV>{});
+    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, ratio, std::make_integer_sequence<int, NV>{});
 
     // positivity limiter (section 4) on the cell's Riemann states
     double th_rho = 1.0, th_p = 1.0;
@@ -417,7 +418,7 @@ hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter
     const long grid = ((nblk + 7) / 8) * 8;   // every XCD gets the same number of slots
     mark(KT_RECON, 1);
     hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, Uin, t.w, w.face, w.theta, w.err,
-                       w.flags_in, g, lim);
+                       w.flags_in, g, lim, (float *)nullptr);
     mark(KT_RECON, 0);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     mark(KT_FLUX, 1);
@@ -438,7 +439,7 @@ hipError_t states_impl(const Geom &g, const Tables &t, const Work &w, const Limi
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;
     hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, w.face, w.theta, w.err,
-                       w.flags_in, g, lim);
+                       w.flags_in, g, lim, (float *)nullptr);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     hipLaunchKernelGGL((k_states<D, R>), dim3(nb), dim3(256), 0, s, U, w.face, w.theta, states, g);
     return hipGetLastError();
@@ -454,6 +455,29 @@ hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const
     if (dim == 2 && R == 3) return rhs_impl<2, 3>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
     if (dim == 3 && R == 2) return rhs_impl<3, 2>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
     if (dim == 3 && R == 3) return rhs_impl<3, 3>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, s, tm);
+    return hipErrorInvalidValue;
+}
+
+template <int D, int R>
+hipError_t ratio_impl(const Geom &g, const Tables &t, const Work &w, const Limiter &lim, const double *U, float *ratio,
+                      hipStream_t s)
+{
+    using C = Cfg<D, R>;
+    const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
+                      (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
+    const long grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, w.face, w.theta, w.err,
+                       (const uint8_t *)nullptr, g, lim, ratio);
+    return hipGetLastError();
+}
+
+hipError_t launch_recon_ratio(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
+                              const double *U, float *ratio, hipStream_t s)
+{
+    if (dim == 2 && R == 2) return ratio_impl<2, 2>(g, t, w, lim, U, ratio, s);
+    if (dim == 2 && R == 3) return ratio_impl<2, 3>(g, t, w, lim, U, ratio, s);
+    if (dim == 3 && R == 2) return ratio_impl<3, 2>(g, t, w, lim, U, ratio, s);
+    if (dim == 3 && R == 3) return ratio_impl<3, 3>(g, t, w, lim, U, ratio, s);
     return hipErrorInvalidValue;
 }
 

@@ -99,10 +99,81 @@ __device__ __forceinline__ double slot_increment(const double (*tile)[Cfg<D, R>:
     return valid ? w - Wc : 0.0;
 }
 
-template <int D, int R, int K, bool BF>
+// ------------------------------------------------------------ learned gate ---
+// The troubled-cell network (n_in -> 32 -> 32 -> 1, GELU) evaluated for the
+// wave's 32 cells on BF16 matrix cores with float32 accumulation.  Its inputs
+// are the increments W_h - W_c of this variable divided by 2^ex, the power of
+// two just above their largest magnitude: in 3D the S0 increments the
+// reconstruction already holds, in 2D the 5 x 5 window around the cell.
+// Operand slots (per lane, 8 BF16 values): W1 [KSG][64], W2 [2][64]; vec holds
+// b1 [32], b2 [32], w3 [32], b3.
+template <int D>
+struct GateShape {
+    static constexpr int NIN = D == 2 ? 25 : 33;
+    static constexpr int KSG = (NIN + 15) / 16;
+    static constexpr int SLOTS = (KSG + 2) * 64;
+};
+
+__device__ __forceinline__ f16v mfma_bf16(uint4 a, uint4 b, f16v c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bh8, a), __builtin_bit_cast(bh8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
+    return (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
+}
+
+// logit of this lane's cell (identical in both half-waves); x holds the lane's
+// KSG x 8 input slots, already scaled to (-1, 1)
+template <int D>
+__device__ __forceinline__ float gate_forward(const float (&x)[GateShape<D>::KSG][8], int lane, const uint4 *Wg,
+                                              const float *vec)
+{
+    constexpr int KSG = GateShape<D>::KSG;
+    const int hf = lane >> 5;
+    f16v acc = {};
+#pragma unroll
+    for (int ks = 0; ks < KSG; ++ks) {
+        const uint4 b = make_uint4(pack_bf16(x[ks][0], x[ks][1]), pack_bf16(x[ks][2], x[ks][3]),
+                                   pack_bf16(x[ks][4], x[ks][5]), pack_bf16(x[ks][6], x[ks][7]));
+        acc = mfma_bf16(Wg[ks * 64 + lane], b, acc);
+    }
+    // first hidden layer: lane holds units 8 (j / 4) + 4 hf + j % 4
+    uint32_t P[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int j0 = 2 * p, j1 = 2 * p + 1;
+        const int m0 = 8 * (j0 / 4) + 4 * hf + j0 % 4, m1 = 8 * (j1 / 4) + 4 * hf + j1 % 4;
+        P[p] = pack_bf16(gelu_f(acc[j0] + vec[m0]), gelu_f(acc[j1] + vec[m1]));
+        asm volatile("" : "+v"(P[p]));
+    }
+    // to the B layout (unit 16 ks + 8 hf + i): swap the pairs each half needs
+    uint32_t rv[4];
+    rv[0] = (uint32_t)__shfl_xor((int)(hf ? P[0] : P[2]), 32, 64);
+    rv[1] = (uint32_t)__shfl_xor((int)(hf ? P[1] : P[3]), 32, 64);
+    rv[2] = (uint32_t)__shfl_xor((int)(hf ? P[4] : P[6]), 32, 64);
+    rv[3] = (uint32_t)__shfl_xor((int)(hf ? P[5] : P[7]), 32, 64);
+    const uint4 b0 = hf ? make_uint4(rv[0], rv[1], P[2], P[3]) : make_uint4(P[0], P[1], rv[0], rv[1]);
+    const uint4 b1 = hf ? make_uint4(rv[2], rv[3], P[6], P[7]) : make_uint4(P[4], P[5], rv[2], rv[3]);
+    f16v acc2 = {};
+    acc2 = mfma_bf16(Wg[(KSG + 0) * 64 + lane], b0, acc2);
+    acc2 = mfma_bf16(Wg[(KSG + 1) * 64 + lane], b1, acc2);
+    float part = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int m = 8 * (j / 4) + 4 * hf + j % 4;
+        part = fmaf(vec[64 + m], gelu_f(acc2[j] + vec[32 + m]), part);
+    }
+    return part + __shfl_xor(part, 32, 64) + vec[96];
+}
+
+template <int D, int R, int K, bool BF, bool GATE>
 __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                           const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                          float *__restrict__ inc, long cell, long ncell, bool active, int sw)
+                                          float *__restrict__ inc, long cell, long ncell, bool active, int sw,
+                                          const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out)
 {
     using C = Cfg<D, R>;
     using M = MixCfg<D, R>;
@@ -142,7 +213,47 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
         bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
-    const bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    if constexpr (GATE) {
+        constexpr int KSG = GateShape<D>::KSG;
+        float gx[KSG][8];
+        if constexpr (D == 3) {
+            // the S0 increments, over 2^ex (ex: amax in [2^(ex-1), 2^ex))
+#pragma unroll
+            for (int ks = 0; ks < KSG; ++ks)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) gx[ks][i] = ks < KS ? (float)ldexp(dl[ks][i], -ex) : 0.f;
+        } else {
+            // 5 x 5 window, slot w = 16 ks + 8 hf + i <-> offset (w / 5 - 2, w % 5 - 2)
+            double gw[KSG][8], gmax = 0.0;
+            int lg = lc;
+#pragma unroll
+            for (int ks = 0; ks < KSG; ++ks) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int wA = 16 * ks + i, wB = 16 * ks + 8 + i;
+                    const int oA = wA < 25 ? (wA / 5 - 2) + C::HX * (wA % 5 - 2) : 0;
+                    const int oB = wB < 25 ? (wB / 5 - 2) + C::HX * (wB % 5 - 2) : 0;
+                    const bool ok = hf ? (wB < 25) : (wA < 25);
+                    const double w = w_component<D, K, C::HN>(tile, lg + (hf ? oB : oA), ph);
+                    gw[ks][i] = ok ? w - Wc : 0.0;
+                    asm volatile("" : "+v"(gw[ks][i]));
+                    gmax = fmax(gmax, fabs(gw[ks][i]));
+                }
+                asm volatile("" : "+v"(lg) : "v"(gw[ks][7]));
+            }
+            gmax = fmax(gmax, __shfl_xor(gmax, 32, 64));
+            int gex = 0;
+            if (gmax > 0.0) frexp(gmax, &gex);
+#pragma unroll
+            for (int ks = 0; ks < KSG; ++ks)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) gx[ks][i] = (float)ldexp(gw[ks][i], -gex);
+        }
+        const float logit = gate_forward<D>(gx, lane, Wg, gvec);
+        use_weno = logit > thr;
+        if (active && hf == 0) fl_out[(long)K * ncell + cell] = use_weno ? 1 : 0;
+    }
     if (__any(use_weno && active)) {
         // smoothness indicators: float32 sums of squares over this lane's four
         // stencils (q = 4 hf + i), in accumulator units squared
@@ -243,14 +354,15 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
     }
 }
 
-template <int D, int R, bool BF, int... K>
+template <int D, int R, bool BF, bool GATE, int... K>
 __device__ __forceinline__ void mixed_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                                const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
                                                float *inc, long cell, long ncell, bool active, int sw,
+                                               const uint4 *Wg, const float *gvec, float thr, uint8_t *fl_out,
                                                std::integer_sequence<int, K...>)
 {
-    ((mixed_var<D, R, K, BF>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al, ph,
-                             flags, inc, cell, ncell, active, sw)),
+    ((mixed_var<D, R, K, BF, GATE>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al,
+                                   ph, flags, inc, cell, ncell, active, sw, Wg, gvec, thr, fl_out)),
      ...);
 }
 
@@ -280,11 +392,11 @@ struct PhiInv {
     }
 };
 
-template <int D, int R, bool BF>
+template <int D, int R, bool BF, bool GATE>
 __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
     float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
-    Geom g, Limiter lim, int sw)
+    Geom g, Limiter lim, int sw, GateArgs ga)
 {
     using C = Cfg<D, R>;
     using M = MixCfg<D, R>;
@@ -293,6 +405,8 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     __shared__ double tile[NV][C::HN];
     __shared__ uint4 As[M::A_FULL];
     __shared__ uint4 Al[M::A_LIN];
+    __shared__ uint4 Wg[GATE ? GateShape<D>::SLOTS : 1];
+    __shared__ float gvec[GATE ? 97 : 1];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
     const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
@@ -312,6 +426,10 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     }
     for (int i = threadIdx.x; i < M::A_FULL; i += M::NT) As[i] = Afull[i];
     for (int i = threadIdx.x; i < M::A_LIN; i += M::NT) Al[i] = Alin[i];
+    if constexpr (GATE) {
+        for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];
+        for (int i = threadIdx.x; i < 97; i += M::NT) gvec[i] = ga.vec[i];
+    }
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;
@@ -332,8 +450,8 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     ph.init(ref, gam);
     // every lane of the wave takes part in the matrix-core work; inactive and
     // non-physical cells compute on their (finite or not) data and store nothing
-    mixed_all_vars<D, R, BF>(tile, lc, lane, As, Al, ph, flags, inc, cell, g.ncell, active && ok, sw,
-                             std::make_integer_sequence<int, NV>{});
+    mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, flags, inc, cell, g.ncell, active && ok, sw, Wg,
+                                   gvec, ga.thr, ga.flags_out, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on) {
@@ -500,7 +618,7 @@ __global__ __launch_bounds__(256) void k_states_mixed(const double *__restrict__
 template <int D, int R, bool BF>
 hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Limiter &lim, int riemann,
                       const double *U0, const double *Uin, double *out, int stage, double dt, double *states,
-                      hipStream_t s, const Timing &tm)
+                      hipStream_t s, const Timing &tm, const GateArgs &ga)
 {
     using C = Cfg<D, R>;
     using M = MixCfg<D, R>;
@@ -509,8 +627,12 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;
     mark(KT_RECON, 1);
-    hipLaunchKernelGGL((k_recon_mixed<D, R, BF>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full, t.lin,
-                       w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw);
+    if (ga.w)
+        hipLaunchKernelGGL((k_recon_mixed<D, R, BF, true>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
+                           t.lin, w.inc32, w.theta, w.err, (const uint8_t *)nullptr, g, lim, t.sw, ga);
+    else
+        hipLaunchKernelGGL((k_recon_mixed<D, R, BF, false>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
+                           t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw, ga);
     mark(KT_RECON, 0);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     if (states) {
@@ -531,6 +653,8 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
 
 bool mixed_supported(int dim, int R) { return !(dim == 3 && R == 3); }
 
+int gate_operand_slots(int dim) { return dim == 2 ? GateShape<2>::SLOTS : GateShape<3>::SLOTS; }
+
 int mixed_operand_slots(int dim, int R, int which)
 {
 #define KF_SLOTS(d, r) return which == 0 ? MixCfg<d, r>::A_FULL : MixCfg<d, r>::A_LIN
@@ -543,11 +667,11 @@ int mixed_operand_slots(int dim, int R, int which)
 
 hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixTables &t, const Work &w,
                             const Limiter &lim, int riemann, const double *U0, const double *Uin, double *out,
-                            int stage, double dt, double *states, hipStream_t s, const Timing &tm)
+                            int stage, double dt, double *states, hipStream_t s, const Timing &tm, const GateArgs &ga)
 {
 #define KF_MIX(d, r)                                                                                              \
-    return bf16 ? mixed_impl<d, r, true>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm)       \
-                : mixed_impl<d, r, false>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm)
+    return bf16 ? mixed_impl<d, r, true>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm, ga)   \
+                : mixed_impl<d, r, false>(g, t, w, lim, riemann, U0, Uin, out, stage, dt, states, s, tm, ga)
     if (dim == 2 && R == 2) KF_MIX(2, 2);
     if (dim == 2 && R == 3) KF_MIX(2, 3);
     if (dim == 3 && R == 2) KF_MIX(3, 2);

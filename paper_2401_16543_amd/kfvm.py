@@ -21,7 +21,8 @@ EXPORTED = [
     "kfvm_init", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream", "kfvm_set_precision",
     "kfvm_set_limiter", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
-    "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags",
+    "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
+    "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step",
 ]
 KERNEL_CLASSES = ("recon", "flux", "update")
 
@@ -78,6 +79,11 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_last_error": ([vp], C.c_char_p),
         "kfvm_set_timing": ([vp, ip], ip),
         "kfvm_set_flags": ([vp, vp], ip),
+        "kfvm_mlp_sizes": ([ip, C.POINTER(ip), C.POINTER(ip)], ip),
+        "kfvm_set_gate": ([vp, vp, C.c_float], ip),
+        "kfvm_get_flags": ([vp, vp], ip),
+        "kfvm_gate_samples": ([vp, vp, vp, vp], ip),
+        "kfvm_mlp_train_step": ([vp, vp, vp, ip, vp, vp, vp, ip, C.c_float, C.c_float, vp, vp, vp], ip),
         "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
         "kfvm_destroy": ([vp], None),
     }
@@ -236,6 +242,55 @@ class KFVM:
             raise ValueError("flags must be a contiguous uint8 CUDA tensor of nvar * ncell entries")
         self._flags = flags
         self._check(self.lib.kfvm_set_flags(self._h, C.c_void_p(flags.data_ptr())))
+
+    # -- learned gate ------------------------------------------------------------
+    def mlp_sizes(self):
+        n_in, n_p = C.c_int(), C.c_int()
+        self._check(self.lib.kfvm_mlp_sizes(self.dim, C.byref(n_in), C.byref(n_p)))
+        return n_in.value, n_p.value
+
+    def set_gate(self, params, threshold: float = 0.0):
+        """params: float32 CUDA tensor of the network (None disables the gate)."""
+        if params is None:
+            self._check(self.lib.kfvm_set_gate(self._h, None, 0.0))
+            return
+        self._gate_params = params.contiguous()
+        self._check(self.lib.kfvm_set_gate(self._h, C.c_void_p(self._gate_params.data_ptr()), float(threshold)))
+
+    def get_flags(self):
+        ncell = 1
+        for x in self.n:
+            ncell *= x
+        out = torch.empty((self.nvar, ncell), dtype=torch.uint8, device="cuda")
+        self._stream()
+        self._check(self.lib.kfvm_get_flags(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def gate_samples(self, U):
+        """(x [nvar, ncell, n_in] float32, omega_0/gamma_0 [nvar, ncell] float32)."""
+        n_in, _ = self.mlp_sizes()
+        ncell = 1
+        for v in self.n:
+            ncell *= v
+        x = torch.empty((self.nvar, ncell, n_in), dtype=torch.float32, device=U.device)
+        r = torch.empty((self.nvar, ncell), dtype=torch.float32, device=U.device)
+        self._stream()
+        self._check(self.lib.kfvm_gate_samples(self._h, self._state(U), C.c_void_p(x.data_ptr()),
+                                               C.c_void_p(r.data_ptr())))
+        return x, r
+
+    def mlp_train_step(self, x, y, params, m=None, v=None, t=1, lr=0.0, pos_weight=1.0, want_grad=False,
+                       want_logits=False):
+        """One step on a batch; returns (loss tensor, grad or None, logits or None)."""
+        B = x.shape[0]
+        ptr = lambda a: C.c_void_p(a.data_ptr()) if a is not None else None
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty_like(params) if want_grad else None
+        logits = torch.empty(B, dtype=torch.float32, device=x.device) if want_logits else None
+        self._stream()
+        self._check(self.lib.kfvm_mlp_train_step(self._h, ptr(x), ptr(y), B, ptr(params), ptr(m), ptr(v), int(t),
+                                                 float(lr), float(pos_weight), ptr(loss), ptr(grad), ptr(logits)))
+        return loss, grad, logits
 
     def set_timing(self, on: bool):
         self._check(self.lib.kfvm_set_timing(self._h, int(on)))

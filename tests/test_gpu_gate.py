@@ -1,0 +1,138 @@
+"""The learned troubled-cell gate on the GPU against the oracle.
+
+* training kernels: gradients and logits against oracle.mlp (same BF16
+  roundings, float64 arithmetic), one Adam step against the oracle's, and loss
+  reduction on a synthetic task;
+* sample export: network inputs and omega_0 / gamma_0 against the oracle;
+* fused inference in the split-precision reconstruction: decisions against
+  the oracle network on the oracle's inputs (disagreements only where the logit
+  sits within float32 noise of the threshold), and the gated right-hand side
+  against the oracle replaying the same decisions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from paper_2401_16543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2401_16543_amd import kfvm
+    kfvm.load_library()
+    return kfvm
+
+
+def _params(n_in, seed, scale=1.0):
+    p = mlp.init_params(n_in, seed=seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 1)
+    p += 0.05 * rng.normal(size=p.shape)        # nonzero biases
+    return (scale * p).astype(np.float32)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_mlp_gradient_matches_oracle(K, d):
+    say(f"case mlp gradient d={d}")
+    dev = K.KFVM(d, (8,) * d, order=5)
+    n_in, P = dev.mlp_sizes()
+    assert P == mlp.n_params(n_in)
+    rng = np.random.default_rng(7)
+    B = 700
+    X = rng.uniform(-1, 1, size=(B, n_in)).astype(np.float32)
+    y = (rng.random(B) < 0.3).astype(np.float32)
+    p = _params(n_in, 3)
+    loss, g, logits = dev.mlp_train_step(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(),
+                                         torch.from_numpy(p).cuda(), lr=0.0, pos_weight=4.0, want_grad=True,
+                                         want_logits=True)
+    z_ref, _ = mlp.forward(p, X, bf16=True)
+    g_ref = mlp.backward(p, X, y, pos_weight=4.0, bf16=True)
+    l_ref = mlp.loss(z_ref, y, 4.0)
+    ez = np.abs(logits.cpu().numpy() - z_ref).max() / np.abs(z_ref).max()
+    eg = np.abs(g.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    say(f"  logits rel {ez:.2e}  grad rel {eg:.2e}  loss {loss.item():.6f} vs {l_ref:.6f}")
+    assert ez <= 1e-4 and eg <= 1e-4
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+
+
+def test_adam_step_and_training(K):
+    say("case adam + training")
+    d = 2
+    dev = K.KFVM(d, (8, 8), order=5)
+    n_in, P = dev.mlp_sizes()
+    rng = np.random.default_rng(11)
+    B = 4096
+    X = rng.uniform(-1, 1, size=(B, n_in)).astype(np.float32)
+    y = ((X[:, 0] * X[:, 7] > 0.1) | (np.abs(X).max(1) > 0.995)).astype(np.float32)
+    p0 = _params(n_in, 5)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    # one Adam step against the oracle's update rule applied to the same gradient
+    pd = torch.from_numpy(p0).cuda()
+    m, v = torch.zeros_like(pd), torch.zeros_like(pd)
+    _, g, _ = dev.mlp_train_step(Xd, yd, pd, lr=0.0, pos_weight=2.0, want_grad=True)
+    dev.mlp_train_step(Xd, yd, pd, m, v, t=1, lr=1e-2, pos_weight=2.0)
+    p1, _, _ = mlp.adam_step(p0.astype(np.float64), g.cpu().numpy().astype(np.float64), 0.0, 0.0, 1, 1e-2)
+    e = np.abs(pd.cpu().numpy() - p1).max()
+    say(f"  adam step max diff {e:.2e}")
+    assert e <= 2e-5
+    # a few hundred steps lower the loss
+    first = None
+    for t in range(2, 400):
+        loss, _, _ = dev.mlp_train_step(Xd, yd, pd, m, v, t=t, lr=3e-3, pos_weight=2.0)
+        if first is None:
+            first = loss.item()
+    last = loss.item()
+    say(f"  loss {first:.4f} -> {last:.4f}")
+    assert last < 0.6 * first
+
+
+@pytest.mark.parametrize("d,n", [(2, 24), (3, 10)])
+def test_gate_samples_match_oracle(K, oracle_mod, d, n):
+    say(f"case samples d={d}")
+    U = inputs.cell_averages(inputs.discontinuous(21, d, 4, 10.0, 100.0), n, 1.4, rule="midpoint", q=4)
+    orc = oracle_mod.Oracle(d, 2, (n,) * d)
+    dev = K.KFVM(d, (n,) * d, order=5)
+    x, r = dev.gate_samples(U.cuda())
+    x_ref, r_ref = orc.gate_inputs(U.numpy()), orc.omega_ratio(U.numpy())
+    ex = np.abs(x.cpu().numpy() - x_ref).max()
+    er = np.abs(r.cpu().numpy() - r_ref).max()
+    say(f"  x max diff {ex:.2e}  ratio max diff {er:.2e}  troubled frac {(1 - r_ref > 0.5).mean():.3f}")
+    assert ex <= 1e-6
+    assert er <= 1e-5
+
+
+@pytest.mark.parametrize("d,n", [(2, 48), (3, 16)])
+def test_fused_gate_decisions_and_replay(K, oracle_mod, d, n):
+    say(f"case fused gate d={d}")
+    U = inputs.cell_averages(inputs.discontinuous(23, d, 6 if d == 2 else 4, 10.0, 100.0), n, 1.4,
+                             rule="midpoint", q=4)
+    orc = oracle_mod.Oracle(d, 2, (n,) * d)
+    dev = K.KFVM(d, (n,) * d, order=5)
+    n_in, _ = dev.mlp_sizes()
+    p = _params(n_in, 9, scale=2.0)
+    z_ref = mlp.forward(p, orc.gate_inputs(U.numpy()).reshape(-1, n_in), bf16=True)[0].reshape(d + 2, -1)
+    thr = float(np.median(z_ref))
+    dev.set_precision("split_f16")
+    dev.set_gate(torch.from_numpy(p).cuda(), thr)
+    dev.set_checking(True)
+    Ud = U.cuda()
+    L = dev.rhs(Ud).cpu().numpy()
+    flags = dev.get_flags().cpu().numpy()
+    want = (z_ref > thr).astype(np.uint8)
+    bad = flags != want
+    near = np.abs(z_ref - thr) <= 2e-3 * (1.0 + np.abs(thr))
+    say(f"  flagged {flags.mean():.3f}  disagreements {int(bad.sum())} (all near threshold: {bool(np.all(near[bad]))})")
+    assert np.all(near[bad]) and bad.mean() <= 0.01
+    # the oracle replaying the GPU's decisions
+    orc.set_flags(flags)
+    ref = orc.rhs(U.numpy())
+    nv = d + 2
+    e = max(np.abs(L[k] - ref[k]).max() / np.abs(ref[k]).max() for k in range(nv))
+    say(f"  gated rhs rel err {e:.2e}")
+    assert e <= 2e-5
