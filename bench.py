@@ -78,9 +78,13 @@ def cpu_baseline(U_host, cfg, budget_s: float):
                       f"{t:.2f} s"}
 
 
-def _time_path(dev, U0, dt, steps, warmup, mode, kfvm, torch):
+def _time_path(dev, U0, dt, steps, warmup, mode, kfvm, torch, gate=None):
     """Warm up on a scratch copy, then time `steps` SSP-RK3 steps from U0."""
     dev.set_precision(mode)
+    if gate is None:
+        dev.set_gate(None)
+    else:
+        dev.set_gate(torch.from_numpy(gate[0]).cuda(), gate[1])
     Uw = U0.clone()
     for _ in range(warmup):
         dev.step(Uw, dt)
@@ -132,8 +136,16 @@ def main():
 
     U_plain, t_plain, kt_plain = _time_path(dev, U0, dt, args.steps, args.warmup, "fp64", kfvm, torch)
     print(f"# plain fp64: {t_plain / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
-    U_mix, t_mix, kt_mix = _time_path(dev, U0, dt, args.steps, args.warmup, args.mixed, kfvm, torch)
-    print(f"# {args.mixed}: {t_mix / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    U_ung, t_ung, kt_ung = _time_path(dev, U0, dt, args.steps, args.warmup, args.mixed, kfvm, torch)
+    print(f"# {args.mixed}: {t_ung / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    l1_ung = float((U_ung[0] - U_plain[0]).abs().mean())
+    del U_ung
+    from paper_2401_16543_amd import gate as gate_mod
+    gp, thr, gmeta = gate_mod.load(d)
+    U_mix, t_mix, kt_mix = _time_path(dev, U0, dt, args.steps, args.warmup, args.mixed, kfvm, torch, (gp, thr))
+    flagged = float(dev.get_flags().float().mean())
+    print(f"# {args.mixed} + learned gate: {t_mix / args.steps * 1e3:.2f} ms/step, flagged {flagged:.4f}",
+          file=sys.stderr, flush=True)
     l1 = float((U_mix[0] - U_plain[0]).abs().mean())
 
     def roof(kt):
@@ -153,14 +165,19 @@ def main():
         "metric": METRIC, "value": ncell * stages / t_mix, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_mix / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ("f16" if args.mixed == "split_f16" else "bf16") + " hi/lo MFMA, f32 acc, f64 epilogue",
+        "dtype": ("f16" if args.mixed == "split_f16" else "bf16") + " hi/lo MFMA, f32 acc, f64 epilogue; bf16 gate",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [n] * d, "R": R, "order": 2 * R + 1,
                    "gamma": gamma, "cfl": cfg["cfl"], "dt": dt, "path": args.mixed, "riemann": "hllc",
-                   "limiter": "on, kappa=0.5", "gate": "none (WENO-AO on every cell)"},
+                   "limiter": "on, kappa=0.5",
+                   "gate": f"learned ({gmeta['samples']} training samples, threshold {thr:.4f}, "
+                           f"held-out false-smooth {gmeta['val_false_smooth']:.4f})"},
+        "gate_flagged_fraction": flagged,
         "l1_rho_vs_fp64": l1,
-        "l1_note": f"mean |rho_mixed - rho_fp64| after {args.steps} steps from the same state and dt; "
-                   f"the FP64 GPU path matches the CPU oracle to ~1e-15",
+        "l1_rho_vs_fp64_ungated": l1_ung,
+        "l1_note": f"mean |rho - rho_fp64| after {args.steps} steps from the same state and dt (the FP64 GPU "
+                   f"path matches the CPU oracle to ~1e-15); ungated = split precision with WENO-AO everywhere, "
+                   f"so the gap between the two is the gate-induced difference",
         "roofline": {"kernel": "k_recon_mixed", "bound": "mfma", "achieved": contraction / mix_avg / 1e12,
                      "peak": 2500.0, "unit": "TFLOP/s", "frac": contraction / mix_avg / 1e12 / 2500.0,
                      "traffic": None, "note": "algorithmic contraction flops (sparse tables, no hi/lo split) "
@@ -168,6 +185,8 @@ def main():
         "kernels_ms_per_launch": per_launch(kt_mix),
         "plain_fp64": {"value": ncell * stages / t_plain, "ms_per_step": t_plain / args.steps * 1e3,
                        "dtype": "f64", "roofline": roof(kt_plain), "kernels_ms_per_launch": per_launch(kt_plain)},
+        "mixed_ungated": {"value": ncell * stages / t_ung, "ms_per_step": t_ung / args.steps * 1e3,
+                          "kernels_ms_per_launch": per_launch(kt_ung)},
         "speedup_vs_plain_fp64": t_plain / t_mix,
     }
     if not args.no_cpu_baseline:

@@ -1,0 +1,175 @@
+"""Training driver of the learned troubled-cell gate (runs on the GPU through
+the library's own kernels; see include/kfvm.h, "learned troubled-cell gate").
+
+Samples come from the method itself: seeded fields are advanced with the FP64
+path, and at snapshots every (variable, cell) yields the gate inputs and the
+WENO-AO ratio omega_0 / gamma_0.  A (variable, cell) is labelled troubled when
+1 - omega_0 / gamma_0 > 0.5, i.e. when the nonlinear weights have moved more
+than half of the full stencil's linear weight onto the substencils.  The
+threshold on the logit is set on held-out samples so that at most 0.1 % of the
+troubled ones are predicted smooth.
+
+    python -m paper_2401_16543_amd.gate --dim 2
+    python -m paper_2401_16543_amd.gate --dim 3
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PARAM_DIR = os.path.join(HERE, "gate_params")
+LABEL_CUT = 0.5           # troubled iff 1 - omega_0/gamma_0 > LABEL_CUT
+FALSE_SMOOTH = 1e-3       # allowed fraction of troubled samples predicted smooth
+
+
+def load(dim: int):
+    """(params float32 array, threshold, metrics dict) of the committed network."""
+    with np.load(os.path.join(PARAM_DIR, f"gate_{dim}d.npz"), allow_pickle=False) as z:
+        params, thr = z["params"].astype(np.float32), float(z["threshold"])
+    with open(os.path.join(PARAM_DIR, f"gate_{dim}d.json")) as f:
+        meta = json.load(f)
+    return params, thr, meta
+
+
+def _fields(dim: int):
+    from . import inputs
+    if dim == 2:
+        n = 512
+        specs = [inputs.discontinuous(100 + i, 2, 6, 10.0, 100.0) for i in range(6)]
+        specs += [inputs.smooth(200 + i, 2, 8) for i in range(2)]
+        snaps = (0, 20, 40)
+    else:
+        n = 128
+        specs = [inputs.discontinuous(300 + i, 3, 4, 10.0, 50.0, M=16) for i in range(4)]
+        specs += [inputs.smooth(400 + i, 3, 16) for i in range(2)]
+        snaps = (0, 10)
+    return n, specs, snaps
+
+
+def generate(dim: int, total: int, seed: int = 0, log=print):
+    """Labelled samples: x [N, n_in] float32 and the ratio [N] (CUDA tensors)."""
+    from . import inputs, kfvm
+    n, specs, snaps = _fields(dim)
+    gamma, cfl = 1.4, 0.4
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    per = total // (len(specs) * len(snaps)) + 1
+    xs, rs = [], []
+    for spec in specs:
+        rule, q = ("gauss", 3) if not spec.regions else ("midpoint", 4 if dim == 2 else 2)
+        U = inputs.cell_averages(spec, n, gamma, rule=rule, q=q, device="cuda")
+        dev = kfvm.KFVM(dim, (n,) * dim, order=5, gamma=gamma)
+        step = 0
+        for target in snaps:
+            while step < target:
+                dev.step(U, dev.cfl_dt(U, cfl))
+                step += 1
+            x, r = dev.gate_samples(U)
+            x, r = x.reshape(-1, x.shape[-1]), r.reshape(-1)
+            pick = torch.randperm(x.shape[0], generator=gen, device="cuda")[:per]
+            xs.append(x[pick].clone())
+            rs.append(r[pick].clone())
+        if dev.status() != kfvm.KFVM_OK:
+            raise RuntimeError("non-physical state while generating samples")
+        dev.close()
+        log(f"  field done: {sum(len(r) for r in rs)} samples")
+    X, Rt = torch.cat(xs)[:total], torch.cat(rs)[:total]
+    return X, Rt
+
+
+def _init_params(n_in: int, seed: int) -> np.ndarray:
+    """Glorot-uniform weights, zero biases, float32, in the flat parameter order."""
+    rng = np.random.default_rng(seed)
+    H = 32
+
+    def glorot(fo, fi):
+        a = np.sqrt(6.0 / (fi + fo))
+        return rng.uniform(-a, a, size=(fo, fi))
+
+    return np.concatenate([glorot(H, n_in).ravel(), np.zeros(H), glorot(H, H).ravel(), np.zeros(H),
+                           glorot(1, H).ravel(), [0.0]]).astype(np.float32)
+
+
+def fit(dev, X, y, epochs: int, batch: int, lr: float, pos_weight: float, seed: int = 0, log=print):
+    n_in, P = dev.mlp_sizes()
+    params = torch.from_numpy(_init_params(n_in, seed)).cuda()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    gen = torch.Generator(device="cuda").manual_seed(seed + 1)
+    t = 0
+    steps = epochs * (X.shape[0] // batch)
+    for ep in range(epochs):
+        perm = torch.randperm(X.shape[0], generator=gen, device="cuda")
+        tot = 0.0
+        nb = X.shape[0] // batch
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            t += 1
+            cur = lr * 0.5 * (1 + np.cos(np.pi * min(t, steps) / steps))    # cosine decay
+            loss, _, _ = dev.mlp_train_step(X[idx].contiguous(), y[idx].contiguous(), params, m, v, t=t,
+                                            lr=max(cur, 1e-5), pos_weight=pos_weight)
+            if b % 50 == 0:
+                tot = loss.item()
+        log(f"  epoch {ep}: loss {tot:.4f}")
+    return params
+
+
+def logits(dev, params, X, batch: int = 65536):
+    out = []
+    for b in range(0, X.shape[0], batch):
+        _, _, z = dev.mlp_train_step(X[b:b + batch].contiguous(), None, params, lr=0.0, want_logits=True)
+        out.append(z)
+    return torch.cat(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dim", type=int, default=2)
+    ap.add_argument("--samples", type=int, default=4_000_000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--out", default=PARAM_DIR)
+    args = ap.parse_args()
+    from . import kfvm
+    log = lambda *a: print(*a, flush=True)
+    t0 = time.time()
+    log(f"gate {args.dim}D: generating {args.samples} samples")
+    X, ratio = generate(args.dim, args.samples, log=log)
+    y = ((1.0 - ratio) > LABEL_CUT).float()
+    N = X.shape[0]
+    n_val = N // 10
+    Xv, yv, Xt, yt = X[:n_val], y[:n_val], X[n_val:], y[n_val:]
+    frac = float(yt.mean())
+    pos_weight = float(min(20.0, max(1.0, (1 - frac) / max(frac, 1e-6))))
+    log(f"  {N} samples, troubled fraction {frac:.4f}, pos_weight {pos_weight:.2f} ({time.time() - t0:.0f} s)")
+    dev = kfvm.KFVM(args.dim, (8,) * args.dim, order=5)
+    params = fit(dev, Xt, yt, args.epochs, args.batch, args.lr, pos_weight, log=log)
+    zv = logits(dev, params, Xv)
+    pos = zv[yv > 0.5]
+    thr = float(torch.quantile(pos.double(), FALSE_SMOOTH)) - 1e-6 if pos.numel() else 0.0
+    pred = zv > thr
+    false_smooth = float(((~pred) & (yv > 0.5)).sum()) / max(1, int((yv > 0.5).sum()))
+    false_troubled = float((pred & (yv < 0.5)).sum()) / max(1, int((yv < 0.5).sum()))
+    flagged = float(pred.float().mean())
+    meta = dict(dim=args.dim, samples=N, troubled_fraction=frac, pos_weight=pos_weight, epochs=args.epochs,
+                batch=args.batch, lr=args.lr, threshold=thr, val_false_smooth=false_smooth,
+                val_false_troubled=false_troubled, val_flagged=flagged,
+                label=f"troubled iff 1 - omega_0/gamma_0 > {LABEL_CUT} (FP64 WENO-AO)",
+                fields="2D: 6 discontinuous + 2 smooth 512^2 fields, snapshots at steps 0, 20, 40"
+                if args.dim == 2 else "3D: 4 discontinuous + 2 smooth 128^3 fields, snapshots at steps 0, 10",
+                seconds=time.time() - t0)
+    os.makedirs(args.out, exist_ok=True)
+    np.savez(os.path.join(args.out, f"gate_{args.dim}d.npz"), params=params.cpu().numpy(), threshold=thr)
+    with open(os.path.join(args.out, f"gate_{args.dim}d.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    log(json.dumps(meta))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
