@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--mixed", default="split_f16", help="split_f16 or split_bf16")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -126,6 +128,12 @@ def main():
     import torch
     from paper_2401_16543_amd import inputs, kfvm
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        print("# copy calibration: 1073741824 bytes read, 1073741824 bytes written", file=sys.stderr, flush=True)
+        del src, dst
     U0, cfg = inputs.config_state(args.workload, device="cuda")
     d, n, R, gamma = cfg["d"], cfg["n"], cfg["R"], cfg["gamma"]
     ncell = n ** d

@@ -18,13 +18,14 @@ namespace dev {
 constexpr double EPS_WENO = 1e-40;
 constexpr int ERR_NONPHYSICAL = -3;
 
-template <int D, int R>
+// Tile of cells per workgroup plus its R-cell halo (3D depth selectable).
+template <int D, int R, int TZ_ = (D == 2 ? 1 : 4)>
 struct Cfg {
     using S = Stencil<D, R>;
     static constexpr S st{};
     static constexpr int TX = D == 2 ? 16 : 8;
     static constexpr int TY = D == 2 ? 16 : 8;
-    static constexpr int TZ = D == 2 ? 1 : 4;
+    static constexpr int TZ = D == 2 ? 1 : TZ_;
     static constexpr int NT = TX * TY * TZ;
     static constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = D == 3 ? TZ + 2 * R : 1;
     static constexpr int HN = HX * HY * HZ;

@@ -39,6 +39,11 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int SB = 13;   // per-cell increment scale: max |delta| * 2^(SB - e) in [2^13, 2^14)
 
+// 3D tiles are 8 x 8 x 8 here: 1024 threads share one copy of the operand
+// tables in LDS (two lanes per cell), four waves per SIMD
+template <int D, int R>
+using MCfg = Cfg<D, R, (D == 3 ? 8 : 1)>;
+
 template <int D, int R>
 struct MixCfg {
     using S = Stencil<D, R>;
@@ -49,7 +54,7 @@ struct MixCfg {
     static constexpr int NTL = (S::NPTS + 31) / 32;             // S0-only tiles
     static constexpr int A_FULL = NTF * KS * 2 * 64;            // 16-byte operand slots
     static constexpr int A_LIN = NTL * KS * 2 * 64;
-    static constexpr int NT = 2 * Cfg<D, R>::NT;                // two lanes per cell
+    static constexpr int NT = 2 * MCfg<D, R>::NT;                // two lanes per cell
 };
 
 template <bool BF>
@@ -86,10 +91,10 @@ __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uin
 
 // increment of variable K at S0 point kk (0 for padding), LDS offset folded in
 template <int D, int R, int K>
-__device__ __forceinline__ double slot_increment(const double (*tile)[Cfg<D, R>::HN], int lc, int hf, int kA, int kB,
+__device__ __forceinline__ double slot_increment(const double (*tile)[MCfg<D, R>::HN], int lc, int hf, int kA, int kB,
                                                  const PhiRows<D> &ph, double Wc)
 {
-    using C = Cfg<D, R>;
+    using C = MCfg<D, R>;
     constexpr int N0 = C::S::N0;
     const int oA = kA < N0 ? C::st.off[kA][0] + C::HX * (C::st.off[kA][1] + C::HY * C::st.off[kA][2]) : 0;
     const int oB = kB < N0 ? C::st.off[kB][0] + C::HX * (C::st.off[kB][1] + C::HY * C::st.off[kB][2]) : 0;
@@ -170,12 +175,12 @@ __device__ __forceinline__ float gate_forward(const float (&x)[GateShape<D>::KSG
 }
 
 template <int D, int R, int K, bool BF, bool GATE>
-__device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
+__device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                           const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
                                           float *__restrict__ inc, long cell, long ncell, bool active, int sw,
                                           const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out)
 {
-    using C = Cfg<D, R>;
+    using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
     using S = typename C::S;
     constexpr int NV = C::NV, NST = S::NST, NPTS = S::NPTS, NROWS = S::NROWS, KS = M::KS;
@@ -355,7 +360,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[Cfg<D, R>::HN], i
 }
 
 template <int D, int R, bool BF, bool GATE, int... K>
-__device__ __forceinline__ void mixed_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, int lane, const uint4 *As,
+__device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                                const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
                                                float *inc, long cell, long ncell, bool active, int sw,
                                                const uint4 *Wg, const float *gvec, float thr, uint8_t *fl_out,
@@ -398,7 +403,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
     Geom g, Limiter lim, int sw, GateArgs ga)
 {
-    using C = Cfg<D, R>;
+    using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
     using S = typename C::S;
     constexpr int NV = C::NV, NPTS = S::NPTS;
@@ -455,23 +460,26 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
 
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on) {
+        // bounds over the 3^d block; the two half-waves take alternate neighbours
         double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
         bool nb_ok = true;
+        constexpr int NB = D == 3 ? 27 : 9;
 #pragma unroll 1
-        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-#pragma unroll 1
-            for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll 1
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int o = lc + dx + C::HX * (dy + C::HY * dz);
-                    double un[NV];
+        for (int nbi = hf; nbi < NB; nbi += 2) {
+            const int dx = nbi % 3 - 1, dy = (nbi / 3) % 3 - 1, dz = D == 3 ? nbi / 9 - 1 : 0;
+            const int o = lc + dx + C::HX * (dy + C::HY * dz);
+            double un[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) un[v] = tile[v][o];
-                    nb_ok = nb_ok && admissible<D>(un, gam);
-                    rmax = fmax(rmax, un[0]);
-                    rmin = fmin(rmin, un[0]);
-                    pmin = fmin(pmin, pressure<D>(un, gam));
-                }
+            for (int v = 0; v < NV; ++v) un[v] = tile[v][o];
+            nb_ok = nb_ok && admissible<D>(un, gam);
+            rmax = fmax(rmax, un[0]);
+            rmin = fmin(rmin, un[0]);
+            pmin = fmin(pmin, pressure<D>(un, gam));
+        }
+        rmax = fmax(rmax, __shfl_xor(rmax, 32, 64));
+        rmin = fmin(rmin, __shfl_xor(rmin, 32, 64));
+        pmin = fmin(pmin, __shfl_xor(pmin, 32, 64));
+        nb_ok = nb_ok && __shfl_xor((int)nb_ok, 32, 64);
         if (!nb_ok && active) *err = ERR_NONPHYSICAL;
         rmax *= 1.0 + lim.kappa;
         rmin *= 1.0 - lim.kappa;
@@ -497,7 +505,11 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
                 pi.apply(w, d);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
-                if (pressure<D>(u, gam) >= pmin) continue;
+                // p >= pmin  <=>  (gamma-1) (E rho - |m|^2 / 2) >= pmin rho   (rho > 0 here)
+                double mm = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) mm += u[1 + a] * u[1 + a];
+                if (u[0] > 0.0 && (gam - 1.0) * (u[D + 1] * u[0] - 0.5 * mm) >= pmin * u[0]) continue;
                 double lo = 0.0, hi = 1.0;
 #pragma unroll 1
                 for (int it = 0; it < 60; ++it) {
@@ -620,7 +632,7 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
                       const double *U0, const double *Uin, double *out, int stage, double dt, double *states,
                       hipStream_t s, const Timing &tm, const GateArgs &ga)
 {
-    using C = Cfg<D, R>;
+    using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
     auto mark = [&](int kind, int begin) { if (tm.on) tm.record(tm.self, kind, s, begin); };
     const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
