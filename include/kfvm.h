@@ -125,7 +125,8 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
  * KFVM_FP64 (default), or split hi/lo half-precision operands on the matrix
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
  * nonlinear-weight normalisation, the limiter, the Riemann solver and the
- * Runge-Kutta update stay in float64. */
+ * Runge-Kutta update stay in float64.  The split modes need fewer than 2^30
+ * cells and are not available for 3D order 7 (KFVM_ERR_ARG). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 
 /* Positivity limiter of section 4 with flattener eta = 0: enabled != 0 turns it

@@ -162,7 +162,8 @@ void build_operands(const double *tab, bool bf16, int sw, std::vector<uint16_t> 
 {
     constexpr kfvm::Stencil<D, R> st{};
     using S = kfvm::Stencil<D, R>;
-    constexpr int KS = (S::N0 + 15) / 16, NTF = (S::NROWS * 8 + 31) / 32, NTL = (S::NPTS + 31) / 32;
+    constexpr int NK = S::N0 - 1;        // contraction slots: S0 less its centre
+    constexpr int KS = (NK + 15) / 16, NTF = (S::NROWS * 8 + 31) / 32, NTL = (S::NPTS + 31) / 32;
     int pos[S::NST][S::N0];
     for (int q = 0; q < S::NST; ++q) {
         for (int h = 0; h < S::N0; ++h) pos[q][h] = -1;
@@ -185,8 +186,9 @@ void build_operands(const double *tab, bool bf16, int sw, std::vector<uint16_t> 
                     const int row = 32 * t + lane % 32, k = 16 * ks + 8 * (lane / 32) + i;
                     const int tau = row / 8, q = row % 8;
                     double w = 0.0;
-                    if (q < S::NST && tau < S::NROWS && k < S::N0 && pos[q][k] >= 0)
-                        w = tab[st.tab[q] + tau * st.nmem[q] + pos[q][k]];
+                    const int h = k < NK ? kfvm::slot_point<D, R>(k) : -1;
+                    if (q < S::NST && tau < S::NROWS && h >= 0 && pos[q][h] >= 0)
+                        w = tab[st.tab[q] + tau * st.nmem[q] + pos[q][h]];
                     put(full, t, ks, lane, i, w);
                 }
     for (int t = 0; t < NTL; ++t)
@@ -194,7 +196,8 @@ void build_operands(const double *tab, bool bf16, int sw, std::vector<uint16_t> 
             for (int lane = 0; lane < 64; ++lane)
                 for (int i = 0; i < 8; ++i) {
                     const int tau = 32 * t + lane % 32, k = 16 * ks + 8 * (lane / 32) + i;
-                    const double w = (tau < S::NPTS && k < S::N0) ? tab[st.tab[0] + tau * S::N0 + k] : 0.0;
+                    const double w = (tau < S::NPTS && k < NK) ? tab[st.tab[0] + tau * S::N0 + kfvm::slot_point<D, R>(k)]
+                                                               : 0.0;
                     put(lin, t, ks, lane, i, w);
                 }
 }
@@ -202,6 +205,8 @@ void build_operands(const double *tab, bool bf16, int sw, std::vector<uint16_t> 
 int prepare_mixed(kfvm_ctx *c, int mode)
 {
     if (c->mix_mode == mode) return KFVM_OK;
+    // the kernels address the face buffer with 32-bit per-lane byte offsets
+    if (c->geom.ncell >= (1L << 30)) return fail(c, KFVM_ERR_ARG, "the split-precision path takes fewer than 2^30 cells");
     const bool bf16 = mode == KFVM_SPLIT_BF16;
     double wmax = 0.0;
     for (double x : c->host_tables) wmax = std::fmax(wmax, std::fabs(x));
@@ -483,14 +488,15 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
     const int nin = kfvm::mlp_n_in(c->dim), P = kfvm::mlp_n_params(c->dim), H = 32;
     std::vector<float> p(P);
     HIP_TRY(c, hipMemcpy(p.data(), params, sizeof(float) * P, hipMemcpyDeviceToHost));
-    const int ksg = (nin + 15) / 16, slots = kfvm::gate_operand_slots(c->dim);
+    const int slots = kfvm::gate_operand_slots(c->dim), ksg = slots / 64 - 2, w1e = kfvm::gate_w1_exp(c->dim);
     std::vector<uint16_t> w((size_t)slots * 8, 0);
-    // W1 as the A operand of k-step ks: lane l holds W1[l % 32][16 ks + 8 (l / 32) + i]
+    // W1 as the A operand of k-step ks: lane l holds W1[l % 32][input of column 16 ks + 8 (l / 32) + i],
+    // times 2^w1e (an exact exponent shift of the BF16 value)
     for (int ks = 0; ks < ksg; ++ks)
         for (int l = 0; l < 64; ++l)
             for (int i = 0; i < 8; ++i) {
-                const int m = l % 32, k = 16 * ks + 8 * (l / 32) + i;
-                w[((size_t)ks * 64 + l) * 8 + i] = k < nin ? to_bf16(p[m * nin + k]) : 0;
+                const int m = l % 32, in = kfvm::gate_slot_input(c->dim, 16 * ks + 8 * (l / 32) + i);
+                w[((size_t)ks * 64 + l) * 8 + i] = in >= 0 ? to_bf16(std::ldexp((double)p[m * nin + in], w1e)) : 0;
             }
     const float *W2 = p.data() + H * nin + H;
     for (int ks = 0; ks < 2; ++ks)

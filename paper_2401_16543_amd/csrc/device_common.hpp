@@ -34,11 +34,17 @@ struct Cfg {
 
 // linear weights, evaluated as (1 - g_hi) g_lo and (1 - g_hi)(1 - g_lo) / (2 D)
 template <int D>
-__device__ __forceinline__ double lin_w(int q)
+__host__ __device__ constexpr double lin_w(int q)
 {
     constexpr double ghi = 0.8, glo = 0.8;
     return q == 0 ? ghi : (q == 1 ? (1.0 - ghi) * glo : (1.0 - ghi) * (1.0 - glo) / (2 * D));
 }
+
+// gamma_q / gamma_0 and 1 / gamma_0 (folded at compile time)
+template <int D>
+__host__ __device__ constexpr double lin_ratio(int q) { return lin_w<D>(q) / lin_w<D>(0); }
+template <int D>
+__host__ __device__ constexpr double inv_lin0() { return 1.0 / lin_w<D>(0); }
 
 // Blocks are handed to the 8 XCDs round-robin; give XCD k the k-th contiguous
 // eighth of the tiles so neighbouring tiles share an L2.
@@ -79,47 +85,54 @@ __device__ __forceinline__ bool admissible(const double *u, double gam)
     return ok && u[0] > 0.0 && pressure<D>(u, gam) > 0.0;
 }
 
-// Phi^-1 w for the reference state (eq. primMat; dE/du_i = rho u_i), dense
-// row order as a matrix-vector product.
-template <int D>
-__device__ __forceinline__ void phi_inv_apply(const double *ref, double gam, const double *w, double *u)
+// 1/x from the hardware estimate and two Newton-Raphson steps r <- r + r (1 - x r)
+// (each squares the relative error): within an ulp or so of the rounded
+// quotient, for positive normal x, at half the cost of an IEEE division.
+__device__ __forceinline__ double rcp64(double x)
 {
-    constexpr int NV = D + 2, E = D + 1;
-    const double rho = ref[0];
-    double vel[D], uu = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
-    double M[NV][NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) M[i][j] = 0.0;
-    M[0][0] = 1.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        M[1 + a][0] = vel[a];
-        M[1 + a][1 + a] = rho;
-        M[E][1 + a] = rho * vel[a];
-    }
-    M[E][0] = uu / 2.0;
-    M[E][E] = 1.0 / (gam - 1.0);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) s += M[i][j] * w[j];
-        u[i] = s;
-    }
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
+
+// Phi^-1 at a reference state (eq. primMat; dE/du_i = rho u_i), applied to a
+// vector of reconstruction variables in the row order of the dense product.
+template <int D>
+struct PhiInv {
+    double rho, vel[D], rvel[D], uu2, inv_gm1;
+    __device__ __forceinline__ void init(const double *ref, double gam)
+    {
+        rho = ref[0];
+        const double ir = rcp64(rho);
+        double uu = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] * ir; uu += vel[a] * vel[a]; rvel[a] = rho * vel[a]; }
+        uu2 = uu / 2.0;
+        inv_gm1 = 1.0 / (gam - 1.0);
+    }
+    __device__ __forceinline__ void apply(const double *w, double *u) const
+    {
+        u[0] = w[0];
+        double e = uu2 * w[0];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            u[1 + a] = vel[a] * w[0] + rho * w[1 + a];
+            e += rvel[a] * w[1 + a];
+        }
+        u[D + 1] = e + inv_gm1 * w[D + 1];
+    }
+};
 
 // Limited Riemann state: u = Phi^-1 w, then the density and pressure scalings
 // about the cell average, each only when it is active (section 4.2).
 template <int D>
-__device__ __forceinline__ void limited_state(const double *ref, double gam, const double *w, double th_rho,
+__device__ __forceinline__ void limited_state(const double *ref, const PhiInv<D> &pi, const double *w, double th_rho,
                                               double th_p, double *u)
 {
     constexpr int NV = D + 2;
-    phi_inv_apply<D>(ref, gam, w, u);
+    pi.apply(w, u);
     if (th_rho < 1.0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * (u[v] - ref[v]);
@@ -138,13 +151,13 @@ struct PhiRows {
     __device__ __forceinline__ void init(const double *ref, double gam)
     {
         const double rho = ref[0];
+        inv_rho = rcp64(rho);
         double vel[D], uu = 0.0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
-        inv_rho = 1.0 / rho;
+        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] * inv_rho; uu += vel[a] * vel[a]; }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            m_vel[a] = -vel[a] / rho;
+            m_vel[a] = -vel[a] * inv_rho;
             e_mom[a] = (1.0 - gam) * vel[a];
         }
         e0 = (gam - 1.0) * uu / 2.0;
@@ -190,43 +203,49 @@ __device__ __forceinline__ double w_component(const double (*tile)[HN], int o, c
 }
 
 // ----------------------------------------------------------------- Riemann ---
-template <int D>
-__device__ __forceinline__ void phys_flux(const double *u, int a, double p, double *F)
-{
-    const double un = u[1 + a] / u[0];
-    F[0] = u[1 + a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) F[1 + b] = u[1 + b] * un + (b == a ? p : 0.0);
-    F[D + 1] = un * (u[D + 1] + p);
-}
-
 // HLLC (Toro ch. 10) or HLL, wavespeeds of Batten et al. from Roe averages.
+// Quotients by the densities and wave-speed differences go through rcp64.
 template <int D, int A>
 __device__ __forceinline__ void riemann(const double *uL, const double *uR, double gam, int hll, double *F)
 {
     constexpr int NV = D + 2, E = D + 1;
-    const double pL = pressure<D>(uL, gam), pR = pressure<D>(uR, gam);
     const double rL = uL[0], rR = uR[0];
-    double vL[D], vR[D];
+    const double irL = rcp64(rL), irR = rcp64(rR);
+    double vL[D], vR[D], qL = 0.0, qR = 0.0;
 #pragma unroll
-    for (int b = 0; b < D; ++b) { vL[b] = uL[1 + b] / rL; vR[b] = uR[1 + b] / rR; }
-    const double cL = sqrt(gam * pL / rL), cR = sqrt(gam * pR / rR);
-    const double HL = (uL[E] + pL) / rL, HR = (uR[E] + pR) / rR;
-    const double sL = sqrt(rL), sR = sqrt(rR);
+    for (int b = 0; b < D; ++b) {
+        vL[b] = uL[1 + b] * irL;
+        vR[b] = uR[1 + b] * irR;
+        qL += uL[1 + b] * vL[b];
+        qR += uR[1 + b] * vR[b];
+    }
+    const double pL = (gam - 1.0) * (uL[E] - 0.5 * qL), pR = (gam - 1.0) * (uR[E] - 0.5 * qR);
+    const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
+    const double HL = (uL[E] + pL) * irL, HR = (uR[E] + pR) * irR;
+    // Roe weights sqrt(rL) / (sqrt(rL) + sqrt(rR)) and its complement
+    const double sq = sqrt(rR * irL);
+    const double wL = rcp64(1.0 + sq), wR = sq * wL;
     double qt = 0.0, vtA = 0.0;
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-        const double vt = (sL * vL[b] + sR * vR[b]) / (sL + sR);
+        const double vt = wL * vL[b] + wR * vR[b];
         qt += vt * vt;
         if (b == A) vtA = vt;
     }
-    const double Ht = (sL * HL + sR * HR) / (sL + sR);
+    const double Ht = wL * HL + wR * HR;
     const double ct = sqrt((gam - 1.0) * (Ht - 0.5 * qt));
     const double SL = fmin(vL[A] - cL, vtA - ct);
     const double SR = fmax(vR[A] + cR, vtA + ct);
     double FL[NV], FR[NV];
-    phys_flux<D>(uL, A, pL, FL);
-    phys_flux<D>(uR, A, pR, FR);
+    FL[0] = uL[1 + A];
+    FR[0] = uR[1 + A];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        FL[1 + b] = uL[1 + b] * vL[A] + (b == A ? pL : 0.0);
+        FR[1 + b] = uR[1 + b] * vR[A] + (b == A ? pR : 0.0);
+    }
+    FL[E] = vL[A] * (uL[E] + pL);
+    FR[E] = vR[A] * (uR[E] + pR);
     if (SL >= 0.0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = FL[v];
@@ -238,25 +257,27 @@ __device__ __forceinline__ void riemann(const double *uL, const double *uR, doub
         return;
     }
     if (hll) {
+        const double id = rcp64(SR - SL);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) / (SR - SL);
+        for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) * id;
         return;
     }
-    const double Ss = (pR - pL + rL * vL[A] * (SL - vL[A]) - rR * vR[A] * (SR - vR[A]))
-                    / (rL * (SL - vL[A]) - rR * (SR - vR[A]));
+    const double dL = SL - vL[A], dR = SR - vR[A];
+    const double Ss = (pR - pL + rL * vL[A] * dL - rR * vR[A] * dR) / (rL * dL - rR * dR);
     const bool left = Ss >= 0.0;
-    const double SK = left ? SL : SR, rK = left ? rL : rR, pK = left ? pL : pR;
+    const double SK = left ? SL : SR, rK = left ? rL : rR, pK = left ? pL : pR, irK = left ? irL : irR;
+    const double dK = left ? dL : dR;
     double uK[NV], FK[NV], vK[D];
 #pragma unroll
     for (int v = 0; v < NV; ++v) { uK[v] = left ? uL[v] : uR[v]; FK[v] = left ? FL[v] : FR[v]; }
 #pragma unroll
     for (int b = 0; b < D; ++b) vK[b] = left ? vL[b] : vR[b];
-    const double fac = rK * (SK - vK[A]) / (SK - Ss);
+    const double fac = rK * dK * rcp64(SK - Ss);
     double us[NV];
     us[0] = fac;
 #pragma unroll
     for (int b = 0; b < D; ++b) us[1 + b] = fac * (b == A ? Ss : vK[b]);
-    us[E] = fac * (uK[E] / rK + (Ss - vK[A]) * (Ss + pK / (rK * (SK - vK[A]))));
+    us[E] = fac * (uK[E] * irK + (Ss - vK[A]) * (Ss + pK * irK * rcp64(dK)));
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = FK[v] + SK * (us[v] - uK[v]);
 }
@@ -278,13 +299,15 @@ __device__ __forceinline__ double face_weight(int gi)
 }
 
 
-// GELU, tanh form (Hendrycks & Gimpel 2016), float32, with
-// tanh(a) = 1 - 2 / (1 + exp(2a)) on the hardware exponential
+// GELU, tanh form (Hendrycks & Gimpel 2016), float32: 0.5 z (1 + tanh a) with
+// a = sqrt(2/pi) (z + 0.044715 z^3) equals z / (1 + 2^(-2 a log2 e)), taken with
+// the hardware base-2 exponential and reciprocal
 __device__ __forceinline__ float gelu_f(float z)
 {
-    const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __expf(2.f * a));
-    return 0.5f * z * (1.f + t);
+    constexpr float k0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;   // -2 sqrt(2/pi) log2(e)
+    constexpr float k1 = k0 * 0.044715f;
+    const float a = z * fmaf(z * z, k1, k0);
+    return z * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(a));
 }
 
 __device__ __forceinline__ float gelu_grad_f(float z)

@@ -71,6 +71,8 @@ struct GateArgs {
 
 bool mixed_supported(int dim, int R);
 int gate_operand_slots(int dim);
+int gate_slot_input(int dim, int k);   // network input fed by W1 operand column k, or -1
+int gate_w1_exp(int dim);              // power of two folded into the W1 operand
 int mixed_operand_slots(int dim, int R, int which);   // which: 0 full, 1 lin; 16-byte slots
 hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixTables &t, const Work &w,
                             const Limiter &lim, int riemann, const double *U0, const double *Uin, double *out,

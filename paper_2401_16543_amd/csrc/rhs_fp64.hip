@@ -72,14 +72,15 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
         double om[NST], sum = 0.0;
 #pragma unroll
         for (int q = 0; q < NST; ++q) {
-            om[q] = lin_w<D>(q) / (beta[q] * beta[q] + EPS_WENO);
+            om[q] = lin_w<D>(q) * rcp64(beta[q] * beta[q] + EPS_WENO);
             sum += om[q];
         }
+        const double isum = rcp64(sum);
 #pragma unroll
-        for (int q = 0; q < NST; ++q) om[q] /= sum;
-        cq[0] = om[0] / lin_w<D>(0);
+        for (int q = 0; q < NST; ++q) om[q] *= isum;
+        cq[0] = om[0] * inv_lin0<D>();
 #pragma unroll
-        for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_w<D>(q) / lin_w<D>(0);
+        for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_ratio<D>(q);
     }
     if (ratio) ratio[(long)K * ncell + cell] = (float)cq[0];   // omega_0 / gamma_0 (1 when linear)
 #pragma unroll 1
@@ -199,6 +200,8 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
         rmax *= 1.0 + lim.kappa;
         rmin *= 1.0 - lim.kappa;
         pmin *= 1.0 - lim.kappa;
+        PhiInv<D> pi;
+        pi.init(ref, gam);
         // density scaling (eq. ppThetaRho), only the violated side of each bound
 #pragma unroll 1
         for (int s = 0; s < NPTS; ++s) {
@@ -212,7 +215,7 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
             double w[NV], u[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
-            limited_state<D>(ref, gam, w, th_rho, 1.0, u);
+            limited_state<D>(ref, pi, w, th_rho, 1.0, u);
             if (pressure<D>(u, gam) >= pmin) continue;
             double lo = 0.0, hi = 1.0;
 #pragma unroll 1
@@ -243,6 +246,9 @@ __device__ __forceinline__ void lower_face_flux(const double *__restrict__ U, co
     for (int v = 0; v < NV; ++v) { refL[v] = U[v * g.ncell + lower]; refR[v] = U[v * g.ncell + cell]; }
     const double trL = theta[lower], tpL = theta[g.ncell + lower];
     const double trR = theta[cell], tpR = theta[g.ncell + cell];
+    PhiInv<D> piL, piR;
+    piL.init(refL, g.gamma);
+    piR.init(refR, g.gamma);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
 #pragma unroll 1
@@ -254,8 +260,8 @@ __device__ __forceinline__ void lower_face_flux(const double *__restrict__ U, co
             wL[v] = face[(sL * NV + v) * g.ncell + lower];
             wR[v] = face[(sR * NV + v) * g.ncell + cell];
         }
-        limited_state<D>(refL, g.gamma, wL, trL, tpL, uL);
-        limited_state<D>(refR, g.gamma, wR, trR, tpR, uR);
+        limited_state<D>(refL, piL, wL, trL, tpL, uL);
+        limited_state<D>(refR, piR, wR, trR, tpR, uR);
         riemann<D, A>(uL, uR, g.gamma, hll, F);
         const double w = face_weight<D, R>(gi);
 #pragma unroll
@@ -344,12 +350,14 @@ __global__ __launch_bounds__(256) void k_states(const double *__restrict__ U, co
 #pragma unroll
     for (int v = 0; v < NV; ++v) ref[v] = U[v * g.ncell + cell];
     const double tr = theta[cell], tp = theta[g.ncell + cell];
+    PhiInv<D> pi;
+    pi.init(ref, g.gamma);
 #pragma unroll 1
     for (int s = 0; s < NPTS; ++s) {
         double w[NV], u[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
-        limited_state<D>(ref, g.gamma, w, tr, tp, u);
+        limited_state<D>(ref, pi, w, tr, tp, u);
 #pragma unroll
         for (int v = 0; v < NV; ++v) states[(cell * NPTS + s) * NV + v] = u[v];
     }

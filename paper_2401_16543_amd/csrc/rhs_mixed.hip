@@ -47,7 +47,8 @@ using MCfg = Cfg<D, R, (D == 3 ? 8 : 1)>;
 template <int D, int R>
 struct MixCfg {
     using S = Stencil<D, R>;
-    static constexpr int KS = (S::N0 + 15) / 16;               // k-steps of 16
+    static constexpr int NK = S::N0 - 1;                        // S0 without its centre
+    static constexpr int KS = (NK + 15) / 16;                   // k-steps of 16
     static constexpr int NTF = (S::NROWS * 8 + 31) / 32;        // interleaved tiles
     static constexpr int TP_END = (S::NPTS * 8 + 31) / 32;      // tiles holding point rows
     static constexpr int TD_BEGIN = (S::NPTS * 8) / 32;         // first tile holding derivative rows
@@ -56,6 +57,58 @@ struct MixCfg {
     static constexpr int A_LIN = NTL * KS * 2 * 64;
     static constexpr int NT = 2 * MCfg<D, R>::NT;                // two lanes per cell
 };
+
+// ---------------------------------------------------- half-wave exchange ---
+// v_permlane32_swap trades the upper half of its first register with the lower
+// half of its second; with both set to x it returns {x_lo, x_lo} and
+// {x_hi, x_hi} (x_lo: the value of lanes 0-31, x_hi: lanes 32-63).
+__device__ __forceinline__ void halves(uint32_t x, uint32_t &lo, uint32_t &hi)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    lo = r[0];
+    hi = r[1];
+}
+__device__ __forceinline__ void halves(float x, float &lo, float &hi)
+{
+    uint32_t a, b;
+    halves(__builtin_bit_cast(uint32_t, x), a, b);
+    lo = __builtin_bit_cast(float, a);
+    hi = __builtin_bit_cast(float, b);
+}
+__device__ __forceinline__ void halves(double x, double &lo, double &hi)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    uint32_t l0, h0, l1, h1;
+    halves((uint32_t)u, l0, h0);
+    halves((uint32_t)(u >> 32), l1, h1);
+    lo = __builtin_bit_cast(double, (uint64_t)l0 | (uint64_t)l1 << 32);
+    hi = __builtin_bit_cast(double, (uint64_t)h0 | (uint64_t)h1 << 32);
+}
+template <typename T>
+__device__ __forceinline__ T pair_sum(T x) { T a, b; halves(x, a, b); return a + b; }
+template <typename T>
+__device__ __forceinline__ T pair_max(T x) { T a, b; halves(x, a, b); return a > b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T pair_min(T x) { T a, b; halves(x, a, b); return a < b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T lower_half(T x) { T a, b; halves(x, a, b); return a; }
+template <typename T>
+__device__ __forceinline__ T partner(T x, int hf) { T a, b; halves(x, a, b); return hf ? a : b; }
+
+// element at byte offset uoff + off of a kernel-argument array: uoff is
+// wave-uniform (read from the first lane, so it lives in scalar registers) and
+// off a per-lane offset below 2^32, which gives the scalar-base + 32-bit
+// lane-offset addressing form
+template <typename T>
+__device__ __forceinline__ T &at4(T *base, long uoff, uint32_t off)
+{
+    // (the builtin returns a signed int: widen each half through uint32_t)
+    const uint64_t u = (uint64_t)uoff;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    const long us = (long)((uint64_t)lo | (uint64_t)hi << 32);
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<std::remove_const_t<T> *>(base)) + us + off);
+}
 
 template <bool BF>
 __device__ __forceinline__ f16v mfma(uint4 a, uint4 b, f16v c)
@@ -73,9 +126,6 @@ __device__ __forceinline__ f16v mfma(uint4 a, uint4 b, f16v c)
 template <bool BF>
 __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uint32_t &lo)
 {
-    // keep the float32 rounding step: without it the compiler folds the two
-    // truncations into one software-emulated float64 -> half conversion
-    asm volatile("" : "+v"(ya), "+v"(yb));
     if constexpr (BF) {
         const __bf16 ha = (__bf16)ya, hb = (__bf16)yb;
         const __bf16 la = (__bf16)(ya - (float)ha), lb = (__bf16)(yb - (float)hb);
@@ -89,16 +139,18 @@ __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uin
     }
 }
 
-// increment of variable K at S0 point kk (0 for padding), LDS offset folded in
+// increment of variable K at contraction slots kA (lower half-wave) and kB
+// (upper), zero past the last slot; LDS offsets fold into immediates
 template <int D, int R, int K>
 __device__ __forceinline__ double slot_increment(const double (*tile)[MCfg<D, R>::HN], int lc, int hf, int kA, int kB,
                                                  const PhiRows<D> &ph, double Wc)
 {
     using C = MCfg<D, R>;
-    constexpr int N0 = C::S::N0;
-    const int oA = kA < N0 ? C::st.off[kA][0] + C::HX * (C::st.off[kA][1] + C::HY * C::st.off[kA][2]) : 0;
-    const int oB = kB < N0 ? C::st.off[kB][0] + C::HX * (C::st.off[kB][1] + C::HY * C::st.off[kB][2]) : 0;
-    const bool valid = hf ? (kB < N0) : (kA < N0);
+    constexpr int NK = MixCfg<D, R>::NK;
+    const int hA = slot_point<D, R>(kA < NK ? kA : 0), hB = slot_point<D, R>(kB < NK ? kB : 0);
+    const int oA = kA < NK ? C::st.off[hA][0] + C::HX * (C::st.off[hA][1] + C::HY * C::st.off[hA][2]) : 0;
+    const int oB = kB < NK ? C::st.off[hB][0] + C::HX * (C::st.off[hB][1] + C::HY * C::st.off[hB][2]) : 0;
+    const bool valid = hf ? (kB < NK) : (kA < NK);
     const int o = lc + (hf ? oB : oA);
     const double w = w_component<D, K, C::HN>(tile, o, ph);
     return valid ? w - Wc : 0.0;
@@ -109,13 +161,15 @@ __device__ __forceinline__ double slot_increment(const double (*tile)[MCfg<D, R>
 // wave's 32 cells on BF16 matrix cores with float32 accumulation.  Its inputs
 // are the increments W_h - W_c of this variable divided by 2^ex, the power of
 // two just above their largest magnitude: in 3D the S0 increments the
-// reconstruction already holds, in 2D the 5 x 5 window around the cell.
+// reconstruction already holds (its float32 operands are those inputs times
+// 2^(SB+1); W1 carries the factor 2^-(SB+1), an exact exponent shift), in 2D
+// the 5 x 5 window around the cell.  The S0 centre, always zero, has no slot.
 // Operand slots (per lane, 8 BF16 values): W1 [KSG][64], W2 [2][64]; vec holds
 // b1 [32], b2 [32], w3 [32], b3.
 template <int D>
 struct GateShape {
     static constexpr int NIN = D == 2 ? 25 : 33;
-    static constexpr int KSG = (NIN + 15) / 16;
+    static constexpr int KSG = 2;                 // 25 window values / 32 S0 slots
     static constexpr int SLOTS = (KSG + 2) * 64;
 };
 
@@ -130,55 +184,84 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
     return (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
 }
 
-// logit of this lane's cell (identical in both half-waves); x holds the lane's
-// KSG x 8 input slots, already scaled to (-1, 1)
+// 16 accumulator registers from vec[base + unit]: register j holds unit
+// 8 (j / 4) + 4 hf + j % 4 of a 32 x 32 accumulator
+__device__ __forceinline__ f16v unit_regs(const float *vec, int hf)
+{
+    f16v a;
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+        const float4 b = *reinterpret_cast<const float4 *>(vec + 8 * gq + 4 * hf);
+        a[4 * gq + 0] = b.x;
+        a[4 * gq + 1] = b.y;
+        a[4 * gq + 2] = b.z;
+        a[4 * gq + 3] = b.w;
+    }
+    return a;
+}
+
+// logit of this lane's cell (identical in both half-waves); xb: the lane's BF16
+// input operands.  Both layers start their accumulators from the biases.
 template <int D>
-__device__ __forceinline__ float gate_forward(const float (&x)[GateShape<D>::KSG][8], int lane, const uint4 *Wg,
+__device__ __forceinline__ float gate_forward(const uint4 (&xb)[GateShape<D>::KSG], int lane, const uint4 *Wg,
                                               const float *vec)
 {
     constexpr int KSG = GateShape<D>::KSG;
     const int hf = lane >> 5;
-    f16v acc = {};
+    f16v acc = unit_regs(vec, hf);
 #pragma unroll
-    for (int ks = 0; ks < KSG; ++ks) {
-        const uint4 b = make_uint4(pack_bf16(x[ks][0], x[ks][1]), pack_bf16(x[ks][2], x[ks][3]),
-                                   pack_bf16(x[ks][4], x[ks][5]), pack_bf16(x[ks][6], x[ks][7]));
-        acc = mfma_bf16(Wg[ks * 64 + lane], b, acc);
-    }
-    // first hidden layer: lane holds units 8 (j / 4) + 4 hf + j % 4
+    for (int ks = 0; ks < KSG; ++ks) acc = mfma_bf16(Wg[ks * 64 + lane], xb[ks], acc);
     uint32_t P[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-        const int j0 = 2 * p, j1 = 2 * p + 1;
-        const int m0 = 8 * (j0 / 4) + 4 * hf + j0 % 4, m1 = 8 * (j1 / 4) + 4 * hf + j1 % 4;
-        P[p] = pack_bf16(gelu_f(acc[j0] + vec[m0]), gelu_f(acc[j1] + vec[m1]));
+        P[p] = pack_bf16(gelu_f(acc[2 * p]), gelu_f(acc[2 * p + 1]));
         asm volatile("" : "+v"(P[p]));
     }
     // to the B layout (unit 16 ks + 8 hf + i): swap the pairs each half needs
     uint32_t rv[4];
-    rv[0] = (uint32_t)__shfl_xor((int)(hf ? P[0] : P[2]), 32, 64);
-    rv[1] = (uint32_t)__shfl_xor((int)(hf ? P[1] : P[3]), 32, 64);
-    rv[2] = (uint32_t)__shfl_xor((int)(hf ? P[4] : P[6]), 32, 64);
-    rv[3] = (uint32_t)__shfl_xor((int)(hf ? P[5] : P[7]), 32, 64);
+    rv[0] = partner(hf ? P[0] : P[2], hf);
+    rv[1] = partner(hf ? P[1] : P[3], hf);
+    rv[2] = partner(hf ? P[4] : P[6], hf);
+    rv[3] = partner(hf ? P[5] : P[7], hf);
     const uint4 b0 = hf ? make_uint4(rv[0], rv[1], P[2], P[3]) : make_uint4(P[0], P[1], rv[0], rv[1]);
     const uint4 b1 = hf ? make_uint4(rv[2], rv[3], P[6], P[7]) : make_uint4(P[4], P[5], rv[2], rv[3]);
-    f16v acc2 = {};
+    f16v acc2 = unit_regs(vec + 32, hf);
     acc2 = mfma_bf16(Wg[(KSG + 0) * 64 + lane], b0, acc2);
     acc2 = mfma_bf16(Wg[(KSG + 1) * 64 + lane], b1, acc2);
+    const f16v w3 = unit_regs(vec + 64, hf);
     float part = 0.f;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int m = 8 * (j / 4) + 4 * hf + j % 4;
-        part = fmaf(vec[64 + m], gelu_f(acc2[j] + vec[32 + m]), part);
+    for (int j = 0; j < 16; ++j) part = fmaf(w3[j], gelu_f(acc2[j]), part);
+    return pair_sum(part) + vec[96];
+}
+
+// Running bounds of a lane's stored face-point increments (all points of the
+// cell, seen by both half-waves) for the positivity limiter: least and largest
+// density increment, least pressure-row increment, and the sum over the
+// velocity rows of their largest square.
+struct IncBounds {
+    float rlo = INFINITY, rhi = -INFINITY, plo = INFINITY, v2 = 0.f;
+};
+
+template <int D, int K>
+__device__ __forceinline__ void note_increment(IncBounds &b, float x, float &v2k)
+{
+    if constexpr (K == 0) {
+        b.rlo = fminf(b.rlo, x);
+        b.rhi = fmaxf(b.rhi, x);
+    } else if constexpr (K == D + 1) {
+        b.plo = fminf(b.plo, x);
+    } else {
+        v2k = fmaxf(v2k, x * x);
     }
-    return part + __shfl_xor(part, 32, 64) + vec[96];
 }
 
 template <int D, int R, int K, bool BF, bool GATE>
 __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                           const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                          float *__restrict__ inc, long cell, long ncell, bool active, int sw,
-                                          const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out)
+                                          float *__restrict__ inc, uint32_t co, long ncell, bool active, int sw,
+                                          const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out,
+                                          IncBounds &bnd)
 {
     using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
@@ -187,7 +270,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
     const int hf = lane >> 5;
     const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
 
-    // increments over this lane's K slots: slot 16 ks + 8 hf + i
+    // increments over this lane's slots 16 ks + 8 hf + i
     double dl[KS][8];
     double amax = 0.0;
     int lcc = lc;
@@ -201,33 +284,42 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
         }
         asm volatile("" : "+v"(lcc) : "v"(dl[ks][7]));
     }
-    amax = fmax(amax, __shfl_xor(amax, 32, 64));
+    amax = pair_max(amax);
     int ex = 0;
     if (amax > 0.0) frexp(amax, &ex);          // amax in [2^(ex-1), 2^ex)
     const int e = ex - 1;
     const double sc = ldexp(1.0, SB - e);
     const int ue = e - SB - sw;                    // accumulator units: value = acc * 2^ue
+    // scaled increments in float32 (kept as such: otherwise the two roundings
+    // below fold into one software float64 -> half conversion)
+    float ys[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            ys[ks][i] = (float)(dl[ks][i] * sc);
+            asm volatile("" : "+v"(ys[ks][i]));
+        }
     uint4 bh[KS], bl[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         uint32_t h[4], l[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            split_pair<BF>((float)(dl[ks][2 * i] * sc), (float)(dl[ks][2 * i + 1] * sc), h[i], l[i]);
+        for (int i = 0; i < 4; ++i) split_pair<BF>(ys[ks][2 * i], ys[ks][2 * i + 1], h[i], l[i]);
         bh[ks] = make_uint4(h[0], h[1], h[2], h[3]);
         bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
-    bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    bool use_weno = flags ? at4(flags, (long)K * ncell, co) != 0 : true;
     if constexpr (GATE) {
         constexpr int KSG = GateShape<D>::KSG;
-        float gx[KSG][8];
+        uint4 xb[KSG];
         if constexpr (D == 3) {
-            // the S0 increments, over 2^ex (ex: amax in [2^(ex-1), 2^ex))
+            static_assert(KSG == KS, "the 3D gate reads the contraction slots");
 #pragma unroll
             for (int ks = 0; ks < KSG; ++ks)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) gx[ks][i] = ks < KS ? (float)ldexp(dl[ks][i], -ex) : 0.f;
+                xb[ks] = make_uint4(pack_bf16(ys[ks][0], ys[ks][1]), pack_bf16(ys[ks][2], ys[ks][3]),
+                                    pack_bf16(ys[ks][4], ys[ks][5]), pack_bf16(ys[ks][6], ys[ks][7]));
         } else {
             // 5 x 5 window, slot w = 16 ks + 8 hf + i <-> offset (w / 5 - 2, w % 5 - 2)
             double gw[KSG][8], gmax = 0.0;
@@ -239,26 +331,33 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                     const int wA = 16 * ks + i, wB = 16 * ks + 8 + i;
                     const int oA = wA < 25 ? (wA / 5 - 2) + C::HX * (wA % 5 - 2) : 0;
                     const int oB = wB < 25 ? (wB / 5 - 2) + C::HX * (wB % 5 - 2) : 0;
-                    const bool ok = hf ? (wB < 25) : (wA < 25);
+                    const bool okw = hf ? (wB < 25) : (wA < 25);
                     const double w = w_component<D, K, C::HN>(tile, lg + (hf ? oB : oA), ph);
-                    gw[ks][i] = ok ? w - Wc : 0.0;
+                    gw[ks][i] = okw ? w - Wc : 0.0;
                     asm volatile("" : "+v"(gw[ks][i]));
                     gmax = fmax(gmax, fabs(gw[ks][i]));
                 }
                 asm volatile("" : "+v"(lg) : "v"(gw[ks][7]));
             }
-            gmax = fmax(gmax, __shfl_xor(gmax, 32, 64));
+            gmax = pair_max(gmax);
             int gex = 0;
             if (gmax > 0.0) frexp(gmax, &gex);
+            const double gs = ldexp(1.0, -gex);
 #pragma unroll
-            for (int ks = 0; ks < KSG; ++ks)
+            for (int ks = 0; ks < KSG; ++ks) {
+                float gx[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) gx[ks][i] = (float)ldexp(gw[ks][i], -gex);
+                for (int i = 0; i < 8; ++i) gx[i] = (float)(gw[ks][i] * gs);
+                xb[ks] = make_uint4(pack_bf16(gx[0], gx[1]), pack_bf16(gx[2], gx[3]), pack_bf16(gx[4], gx[5]),
+                                    pack_bf16(gx[6], gx[7]));
+            }
         }
-        const float logit = gate_forward<D>(gx, lane, Wg, gvec);
+        const float logit = gate_forward<D>(xb, lane, Wg, gvec);
         use_weno = logit > thr;
-        if (active && hf == 0) fl_out[(long)K * ncell + cell] = use_weno ? 1 : 0;
+        if (active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     }
+    const uint32_t co4 = co * 4u;
+    float v2k = 0.f;
     if (__any(use_weno && active)) {
         // smoothness indicators: float32 sums of squares over this lane's four
         // stencils (q = 4 hf + i), in accumulator units squared
@@ -287,21 +386,20 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
         for (int i = 0; i < 4; ++i) {
             const int q = 4 * hf + i;
             const double beta = ldexp((double)bp[i], 2 * ue);
-            om[i] = q < NST ? lin_w<D>(q) / (beta * beta + EPS_WENO) : 0.0;
+            om[i] = q < NST ? lin_w<D>(q) * rcp64(beta * beta + EPS_WENO) : 0.0;
             part += om[i];
         }
-        const double inv = 1.0 / (part + __shfl_xor(part, 32, 64));
+        const double inv = rcp64(pair_sum(part));
 #pragma unroll
         for (int i = 0; i < 4; ++i) om[i] *= inv;
-        const double other0 = __shfl_xor(om[0], 32, 64);     // every lane takes part in the exchange
-        const double om0 = hf ? other0 : om[0];
+        const double om0 = lower_half(om[0]);
         // WENO-AO coefficients (eq. wenoAOrec) of this lane's stencils, or the
         // linear S0 value for a cell the gate marks smooth
         float cm[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int q = 4 * hf + i;
-            double cq = q == 0 ? om0 / lin_w<D>(0) : (q < NST ? om[i] - om0 * lin_w<D>(q) / lin_w<D>(0) : 0.0);
+            double cq = q == 0 ? om0 * inv_lin0<D>() : (q < NST ? om[i] - om0 * lin_ratio<D>(q) : 0.0);
             if (!use_weno) cq = q == 0 ? 1.0 : 0.0;
             cm[i] = (float)cq;
         }
@@ -324,8 +422,9 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                     float part4 = 0.f;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) part4 += cm[i] * acc[4 * gq + i];
-                    const float tot = part4 + __shfl_xor(part4, 32, 64);
-                    if ((tau & 1) == hf && active) inc[((long)tau * NV + K) * ncell + cell] = ldexpf(tot, ue);
+                    const float val = ldexpf(pair_sum(part4), ue);
+                    note_increment<D, K>(bnd, val, v2k);
+                    if ((tau & 1) == hf && active) at4(inc, 4 * ((long)tau * NV + K) * ncell, co4) = val;
                 }
             }
         }
@@ -344,58 +443,35 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int tau = 32 * t + 8 * (j / 4) + 4 * hf + j % 4;
-                // this lane owns tau; keep the ownership rule (tau & 1) == hf of the
-                // blended path by exchanging with the partner
-                const float v = ldexpf(acc[j], ue);
-                const float other = __shfl_xor(v, 32, 64);
-                const int tau_o = 32 * t + 8 * (j / 4) + 4 * (1 - hf) + j % 4;
-                if (active) {
-                    if (tau < NPTS && (tau & 1) == hf) inc[((long)tau * NV + K) * ncell + cell] = v;
-                    if (tau_o < NPTS && (tau_o & 1) == hf) inc[((long)tau_o * NV + K) * ncell + cell] = other;
+                // register j holds point T0 in the lower half-wave and T0 + 4 in
+                // the upper; both have the parity of T0, so the owner half-wave
+                // (tau & 1) of the blended path stores the two
+                const int T0 = 32 * t + 8 * (j / 4) + j % 4;
+                float vlo, vhi;
+                halves(ldexpf(acc[j], ue), vlo, vhi);
+                if (T0 < NPTS) note_increment<D, K>(bnd, vlo, v2k);
+                if (T0 + 4 < NPTS) note_increment<D, K>(bnd, vhi, v2k);
+                if (active && hf == (T0 & 1)) {
+                    if (T0 < NPTS) at4(inc, 4 * ((long)T0 * NV + K) * ncell, co4) = vlo;
+                    if (T0 + 4 < NPTS) at4(inc, 4 * ((long)(T0 + 4) * NV + K) * ncell, co4) = vhi;
                 }
             }
         }
     }
+    if constexpr (K >= 1 && K <= D) bnd.v2 += v2k;
 }
 
 template <int D, int R, bool BF, bool GATE, int... K>
 __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
                                                const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
-                                               float *inc, long cell, long ncell, bool active, int sw,
+                                               float *inc, uint32_t co, long ncell, bool active, int sw,
                                                const uint4 *Wg, const float *gvec, float thr, uint8_t *fl_out,
-                                               std::integer_sequence<int, K...>)
+                                               IncBounds &bnd, std::integer_sequence<int, K...>)
 {
     ((mixed_var<D, R, K, BF, GATE>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al,
-                                   ph, flags, inc, cell, ncell, active, sw, Wg, gvec, thr, fl_out)),
+                                   ph, flags, inc, co, ncell, active, sw, Wg, gvec, thr, fl_out, bnd)),
      ...);
 }
-
-// Phi^-1 applied to an increment vector (eq. primMat; dE/du_i = rho u_i)
-template <int D>
-struct PhiInv {
-    double rho, vel[D], uu2, inv_gm1;
-    __device__ __forceinline__ void init(const double *ref, double gam)
-    {
-        rho = ref[0];
-        double uu = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) { vel[a] = ref[1 + a] / rho; uu += vel[a] * vel[a]; }
-        uu2 = uu / 2.0;
-        inv_gm1 = 1.0 / (gam - 1.0);
-    }
-    __device__ __forceinline__ void apply(const double *w, double *u) const
-    {
-        u[0] = w[0];
-        double e = uu2 * w[0];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            u[1 + a] = vel[a] * w[0] + rho * w[1 + a];
-            e += rho * vel[a] * w[1 + a];
-        }
-        u[D + 1] = e + inv_gm1 * w[D + 1];
-    }
-};
 
 template <int D, int R, bool BF, bool GATE>
 __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
@@ -408,10 +484,11 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     using S = typename C::S;
     constexpr int NV = C::NV, NPTS = S::NPTS;
     __shared__ double tile[NV][C::HN];
+    __shared__ double ptile[C::HN];      // pressure of each tile cell, -1 where not admissible
     __shared__ uint4 As[M::A_FULL];
     __shared__ uint4 Al[M::A_LIN];
     __shared__ uint4 Wg[GATE ? GateShape<D>::SLOTS : 1];
-    __shared__ float gvec[GATE ? 97 : 1];
+    __shared__ __align__(16) float gvec[GATE ? 100 : 4];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
     const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
@@ -420,14 +497,29 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     if (tb >= nblk) return;
     const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
     const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+    const double gam = g.gamma;
 
     for (int i = threadIdx.x; i < C::HN; i += M::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
         const int gx = wrap_any(x0 + hx, g.n[0]), gy = wrap_any(y0 + hy, g.n[1]);
         const int gz = D == 3 ? wrap_any(z0 + hz, g.n[2]) : 0;
         const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
+        double u[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) tile[v][i] = U[v * g.ncell + cl];
+        for (int v = 0; v < NV; ++v) {
+            u[v] = U[v * g.ncell + cl];
+            tile[v][i] = u[v];
+        }
+        if (lim.on) {
+            double mm = 0.0;
+            bool fin = true;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fin = fin && isfinite(u[v]);
+#pragma unroll
+            for (int a = 0; a < D; ++a) mm += u[1 + a] * u[1 + a];
+            const double p = (gam - 1.0) * (u[D + 1] - 0.5 * mm * rcp64(u[0]));
+            ptile[i] = fin && u[0] > 0.0 && p > 0.0 ? p : -1.0;
+        }
     }
     for (int i = threadIdx.x; i < M::A_FULL; i += M::NT) As[i] = Afull[i];
     for (int i = threadIdx.x; i < M::A_LIN; i += M::NT) Al[i] = Alin[i];
@@ -443,60 +535,67 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
     const bool active = cx < g.n[0] && cy < g.n[1] && (D == 2 || cz < g.n[2]);
     const long cell = active ? cx + (long)g.n[0] * (cy + (long)g.n[1] * cz) : 0;
+    const uint32_t co = (uint32_t)cell;
     const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
 
     double ref[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
-    const double gam = g.gamma;
     const bool ok = admissible<D>(ref, gam);
     if (!ok && active) *err = ERR_NONPHYSICAL;
     PhiRows<D> ph;
     ph.init(ref, gam);
     // every lane of the wave takes part in the matrix-core work; inactive and
     // non-physical cells compute on their (finite or not) data and store nothing
-    mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, flags, inc, cell, g.ncell, active && ok, sw, Wg,
-                                   gvec, ga.thr, ga.flags_out, std::make_integer_sequence<int, NV>{});
+    IncBounds bnd;
+    mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, flags, inc, co, g.ncell, active && ok, sw, Wg, gvec,
+                                   ga.thr, ga.flags_out, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on) {
         // bounds over the 3^d block; the two half-waves take alternate neighbours
         double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
-        bool nb_ok = true;
         constexpr int NB = D == 3 ? 27 : 9;
-#pragma unroll 1
-        for (int nbi = hf; nbi < NB; nbi += 2) {
-            const int dx = nbi % 3 - 1, dy = (nbi / 3) % 3 - 1, dz = D == 3 ? nbi / 9 - 1 : 0;
-            const int o = lc + dx + C::HX * (dy + C::HY * dz);
-            double un[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) un[v] = tile[v][o];
-            nb_ok = nb_ok && admissible<D>(un, gam);
-            rmax = fmax(rmax, un[0]);
-            rmin = fmin(rmin, un[0]);
-            pmin = fmin(pmin, pressure<D>(un, gam));
+        for (int j = 0; j < (NB + 1) / 2; ++j) {
+            const int nA = 2 * j, nB = 2 * j + 1 < NB ? 2 * j + 1 : 2 * j;
+            const int oA = nA % 3 - 1 + C::HX * ((nA / 3) % 3 - 1 + C::HY * (D == 3 ? nA / 9 - 1 : 0));
+            const int oB = nB % 3 - 1 + C::HX * ((nB / 3) % 3 - 1 + C::HY * (D == 3 ? nB / 9 - 1 : 0));
+            const int o = lc + (hf ? oB : oA);
+            const double r = tile[0][o];
+            rmax = fmax(rmax, r);
+            rmin = fmin(rmin, r);
+            pmin = fmin(pmin, ptile[o]);
         }
-        rmax = fmax(rmax, __shfl_xor(rmax, 32, 64));
-        rmin = fmin(rmin, __shfl_xor(rmin, 32, 64));
-        pmin = fmin(pmin, __shfl_xor(pmin, 32, 64));
-        nb_ok = nb_ok && __shfl_xor((int)nb_ok, 32, 64);
-        if (!nb_ok && active) *err = ERR_NONPHYSICAL;
+        rmax = pair_max(rmax);
+        rmin = pair_min(rmin);
+        pmin = pair_min(pmin);
+        if (!(pmin > 0.0) && active) *err = ERR_NONPHYSICAL;   // a neighbour is not admissible
         rmax *= 1.0 + lim.kappa;
         rmin *= 1.0 - lim.kappa;
         pmin *= 1.0 - lim.kappa;
-        PhiInv<D> pi;
-        pi.init(ref, gam);
+        bool exact = false;
         if (active && ok) {
-            // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
-#pragma unroll 1
-            for (int tau = hf; tau < NPTS; tau += 2) {
-                const double rs = ref[0] + (double)inc[((long)tau * NV + 0) * g.ncell + cell];
-                if (rs < rmin) th_rho = fmin(th_rho, (ref[0] - rmin) / (ref[0] - rs));
-                else if (rs > rmax) th_rho = fmin(th_rho, (rmax - ref[0]) / (rs - ref[0]));
-            }
+            // density scaling (eq. ppThetaRho) from the extreme point values: the
+            // smallest ratio of each violated side is taken at its extreme point
+            const double r0 = ref[0];
+            const double rs_lo = r0 + (double)bnd.rlo, rs_hi = r0 + (double)bnd.rhi;
+            if (rs_lo < rmin) th_rho = fmin(th_rho, (r0 - rmin) / (r0 - rs_lo));
+            if (rs_hi > rmax) th_rho = fmin(th_rho, (rmax - r0) / (rs_hi - r0));
+            // pressure at a point, exactly: p = p~ + th dw_p - (gamma-1)/2 th^2 rho~^2 |dw_u|^2 / rho
+            // (dw: its increments in reconstruction variables).  With the least
+            // dw_p and rho and the largest |dw_u|^2 this bounds every point from
+            // below; only a cell whose bound falls under pmin takes the per-point
+            // test and bisection (eq. thetapRoot, eq. thetaP).
+            const double rlo = r0 + th_rho * (double)bnd.rlo;
+            const double plow = ptile[lc] + th_rho * (double)bnd.plo -
+                                0.5 * (gam - 1.0) * th_rho * th_rho * r0 * r0 * (double)bnd.v2 * rcp64(rlo);
+            exact = !(rlo > 0.0 && plow >= pmin);
         }
-        th_rho = fmin(th_rho, __shfl_xor(th_rho, 32, 64));
-        if (active && ok) {
+        if (exact) {
+            PhiInv<D> pi;
+            pi.init(ref, gam);
+            // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
 #pragma unroll 1
             for (int tau = hf; tau < NPTS; tau += 2) {
                 double w[NV], d[NV], u[NV];
@@ -505,11 +604,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
                 pi.apply(w, d);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
-                // p >= pmin  <=>  (gamma-1) (E rho - |m|^2 / 2) >= pmin rho   (rho > 0 here)
-                double mm = 0.0;
-#pragma unroll
-                for (int a = 0; a < D; ++a) mm += u[1 + a] * u[1 + a];
-                if (u[0] > 0.0 && (gam - 1.0) * (u[D + 1] * u[0] - 0.5 * mm) >= pmin * u[0]) continue;
+                if (pressure<D>(u, gam) >= pmin) continue;
                 double lo = 0.0, hi = 1.0;
 #pragma unroll 1
                 for (int it = 0; it < 60; ++it) {
@@ -522,7 +617,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
                 th_p = fmin(th_p, lo);
             }
         }
-        th_p = fmin(th_p, __shfl_xor(th_p, 32, 64));
+        th_p = pair_min(th_p);
     }
     if (active && hf == 0) {
         theta[cell] = th_rho;
@@ -534,28 +629,28 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
 template <int D, int R, int A>
 __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__ U, const float *__restrict__ inc,
                                                       const double *__restrict__ theta, const Geom &g, long cell,
-                                                      long lower, int hll, double *Fbar)
+                                                      long lower, const double *refR, const PhiInv<D> &piR,
+                                                      double thR, int hll, double *Fbar)
 {
     using S = Stencil<D, R>;
     constexpr int NV = D + 2, NG = S::NG;
-    double refL[NV], refR[NV];
+    double refL[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { refL[v] = U[v * g.ncell + lower]; refR[v] = U[v * g.ncell + cell]; }
+    for (int v = 0; v < NV; ++v) refL[v] = U[v * g.ncell + lower];
     const double thL = theta[lower] * theta[g.ncell + lower];
-    const double thR = theta[cell] * theta[g.ncell + cell];
-    PhiInv<D> piL, piR;
+    PhiInv<D> piL;
     piL.init(refL, g.gamma);
-    piR.init(refR, g.gamma);
+    const float *incL = inc + lower, *incR = inc + cell;
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
 #pragma unroll 1
     for (int gi = 0; gi < NG; ++gi) {
         double wL[NV], wR[NV], dL[NV], dR[NV], uL[NV], uR[NV], F[NV];
-        const int sL = (2 * A + 1) * NG + gi, sR = (2 * A + 0) * NG + gi;
+        const long sL = (long)((2 * A + 1) * NG + gi) * NV * g.ncell, sR = (long)((2 * A + 0) * NG + gi) * NV * g.ncell;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            wL[v] = (double)inc[((long)sL * NV + v) * g.ncell + lower];
-            wR[v] = (double)inc[((long)sR * NV + v) * g.ncell + cell];
+            wL[v] = (double)incL[sL + v * g.ncell];
+            wR[v] = (double)incR[sR + v * g.ncell];
         }
         piL.apply(wL, dL);
         piR.apply(wR, dR);
@@ -578,25 +673,32 @@ __global__ __launch_bounds__(256) void k_flux_mixed(const double *__restrict__ U
     if (cell >= g.ncell) return;
     const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
     const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
+    double refR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) refR[v] = U[v * g.ncell + cell];
+    const double thR = theta[cell] * theta[g.ncell + cell];
+    PhiInv<D> piR;
+    piR.init(refR, g.gamma);
+    double *fb = fbar + cell;
     double F[NV];
     bool ok = true;
     {
         const long lower = wrapi(cx - 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
-        lower_face_flux_mixed<D, R, 0>(U, inc, theta, g, cell, lower, hll, F);
+        lower_face_flux_mixed<D, R, 0>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(0 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+        for (int v = 0; v < NV; ++v) { fb[(0 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
     }
     {
         const long lower = cx + (long)g.n[0] * (wrapi(cy - 1, g.n[1]) + (long)g.n[1] * cz);
-        lower_face_flux_mixed<D, R, 1>(U, inc, theta, g, cell, lower, hll, F);
+        lower_face_flux_mixed<D, R, 1>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(1 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+        for (int v = 0; v < NV; ++v) { fb[(1 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
     }
     if constexpr (D == 3) {
         const long lower = cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz - 1, g.n[2]));
-        lower_face_flux_mixed<D, R, 2>(U, inc, theta, g, cell, lower, hll, F);
+        lower_face_flux_mixed<D, R, 2>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(2 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+        for (int v = 0; v < NV; ++v) { fb[(2 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
     }
     if (!ok) *err = ERR_NONPHYSICAL;
 }
@@ -666,6 +768,14 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
 bool mixed_supported(int dim, int R) { return !(dim == 3 && R == 3); }
 
 int gate_operand_slots(int dim) { return dim == 2 ? GateShape<2>::SLOTS : GateShape<3>::SLOTS; }
+
+int gate_slot_input(int dim, int k)
+{
+    if (dim == 2) return k < 25 ? k : -1;
+    return k < MixCfg<3, 2>::NK ? slot_point<3, 2>(k) : -1;
+}
+
+int gate_w1_exp(int dim) { return dim == 2 ? 0 : -(SB + 1); }
 
 int mixed_operand_slots(int dim, int R, int which)
 {

@@ -115,6 +115,25 @@ struct Stencil {
     }
 };
 
+// Contraction slot k of the split-precision path -> S0 index.  The centre is
+// the middle of the lexicographic order of S0 and, its increment W_c - W_c
+// being zero, takes no slot: slots 0 .. N0 - 2.
+template <int D, int R>
+constexpr int slot_point(int k)
+{
+    return k < Stencil<D, R>::N0 / 2 ? k : k + 1;
+}
+
+template <int D, int R>
+constexpr bool centre_is_middle()
+{
+    constexpr Stencil<D, R> s{};
+    constexpr int c = Stencil<D, R>::N0 / 2;
+    return s.off[c][0] == 0 && s.off[c][1] == 0 && s.off[c][2] == 0;
+}
+static_assert(centre_is_middle<2, 2>() && centre_is_middle<2, 3>() && centre_is_middle<3, 2>(),
+              "S0 centre must sit in the middle of the lexicographic order");
+
 // linear weights of section 3.2 (gamma_hi = gamma_lo = 0.8)
 template <int D>
 constexpr double linear_weight(int q)

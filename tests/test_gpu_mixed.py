@@ -99,6 +99,45 @@ def test_gate_flags_replay(K, oracle_mod, mode):
     assert e <= (1e-12 if mode == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("name,mode,tol,gated", [("3d_smooth_256", "split_f16", 2e-6, False),
+                                                  ("3d_smooth_256", "split_f16", 2e-6, True),
+                                                  ("2d_jumps_1024", "split_bf16", 2e-2, False),
+                                                  ("2d_jumps_1024", "split_f16", 2e-5, True)])
+def test_mixed_full_size_sampled(K, oracle_mod, name, mode, tol, gated):
+    """Full-size workloads in the benchmark's launch configuration: the
+    split-precision RHS over the whole grid (with the trained gate, the oracle
+    replaying its decisions) against the oracle at sampled cells, and
+    conservation.  Face-buffer offsets pass 2^31 bytes here."""
+    from paper_2401_16543_amd import gate
+    say(f"case mixed full-size {name} {mode} gated={gated}")
+    U, cfg = inputs.config_state(name, device="cuda")
+    d, n, R, gamma = cfg["d"], cfg["n"], cfg["R"], cfg["gamma"]
+    dev = K.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
+    dev.set_precision(mode)
+    dev.set_checking(True)
+    if gated:
+        params, thr, _ = gate.load(d)
+        dev.set_gate(torch.from_numpy(params).cuda(), thr)
+    L = dev.rhs(U)
+    torch.cuda.synchronize()
+    Lh = L.cpu().numpy().reshape(d + 2, -1)
+    Uh = U.cpu().numpy()
+    ncell = n ** d
+    rng = np.random.default_rng(8)
+    cells = np.concatenate([[0, ncell - 1, n - 1, ncell - n], rng.integers(0, ncell, 160 if d == 3 else 600)])
+    orc = oracle_mod.Oracle(d, R, (n,) * d, gamma=gamma)
+    if gated:
+        flags = dev.get_flags().cpu().numpy()
+        say(f"  flagged {flags.mean():.4f}")
+        orc.set_flags(flags)
+    ref = orc.rhs_cells(Uh, cells)
+    err = (np.abs(Lh[:, cells].T - ref) / np.abs(Lh).max(axis=1)).max()
+    say(f"  sampled rel err {err:.3e}")
+    assert err <= tol
+    tot = np.abs(Lh.sum(axis=1)) / np.abs(Lh).sum(axis=1)
+    assert np.all(tot <= 1e-13)
+
+
 def test_mixed_trajectory_smooth_l1(K):
     """10 SSP-RK3 steps of the 64^2 smooth workload: L1 density difference between
     the split-FP16 and FP64 paths stays far below 1e-8."""
