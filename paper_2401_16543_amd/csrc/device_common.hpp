@@ -66,25 +66,6 @@ __device__ __forceinline__ int wrap_any(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-template <int D>
-__device__ __forceinline__ double pressure(const double *u, double gam)
-{
-    double ke = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) ke += u[1 + a] * u[1 + a];
-    ke = 0.5 * ke / u[0];
-    return (gam - 1.0) * (u[D + 1] - ke);
-}
-
-template <int D>
-__device__ __forceinline__ bool admissible(const double *u, double gam)
-{
-    bool ok = true;
-#pragma unroll
-    for (int v = 0; v < D + 2; ++v) ok = ok && isfinite(u[v]);
-    return ok && u[0] > 0.0 && pressure<D>(u, gam) > 0.0;
-}
-
 // 1/x from the hardware estimate and two Newton-Raphson steps r <- r + r (1 - x r)
 // (each squares the relative error): within an ulp or so of the rounded
 // quotient, for positive normal x, at half the cost of an IEEE division.
@@ -95,6 +76,24 @@ __device__ __forceinline__ double rcp64(double x)
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+}
+
+template <int D>
+__device__ __forceinline__ double pressure(const double *u, double gam)
+{
+    double ke = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ke += u[1 + a] * u[1 + a];
+    return (gam - 1.0) * (u[D + 1] - 0.5 * ke * rcp64(u[0]));
+}
+
+template <int D>
+__device__ __forceinline__ bool admissible(const double *u, double gam)
+{
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) ok = ok && isfinite(u[v]);
+    return ok && u[0] > 0.0 && pressure<D>(u, gam) > 0.0;
 }
 
 // Phi^-1 at a reference state (eq. primMat; dE/du_i = rho u_i), applied to a

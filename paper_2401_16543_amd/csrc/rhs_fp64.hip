@@ -26,13 +26,22 @@ namespace kfvm {
 namespace {
 using namespace dev;
 
+// Running bounds of a cell's face-point values for the positivity limiter:
+// least and largest density, and, as increments over the cell's own W, the
+// least pressure-row value and the sum over the velocity rows of their
+// largest square.
+struct FaceBounds {
+    double rlo = INFINITY, rhi = -INFINITY, plo = INFINITY, v2 = 0.0;
+};
+
 // Reconstruction of variable K of W at every face point of one cell: smoothness
 // indicators (eq. smoothIndic), nonlinear weights (eq. nlinWts) and the WENO-AO
 // blend (eq. wenoAOrec), or the linear S0 value when the gate says so.
 template <int D, int R, int K>
 __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
                                           const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                          double *__restrict__ face, long cell, long ncell, float *__restrict__ ratio)
+                                          double *__restrict__ face, long cell, long ncell, float *__restrict__ ratio,
+                                          FaceBounds &fb)
 {
     using C = Cfg<D, R>;
     using S = typename C::S;
@@ -83,6 +92,8 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
         for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_ratio<D>(q);
     }
     if (ratio) ratio[(long)K * ncell + cell] = (float)cq[0];   // omega_0 / gamma_0 (1 when linear)
+    const double Wc = gv[N0 / 2];                                // the cell's own W (S0 centre)
+    double v2k = 0.0;
 #pragma unroll 1
     for (int s = 0; s < NPTS; ++s) {
         double v[NST];
@@ -104,19 +115,28 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
             for (int q = 1; q < NST; ++q) f += cq[q] * v[q];
         }
         face[(s * NV + K) * ncell + cell] = f;
+        if constexpr (K == 0) {
+            fb.rlo = fmin(fb.rlo, f);
+            fb.rhi = fmax(fb.rhi, f);
+        } else if constexpr (K == D + 1) {
+            fb.plo = fmin(fb.plo, f - Wc);
+        } else {
+            v2k = fmax(v2k, (f - Wc) * (f - Wc));
+        }
     }
+    if constexpr (K >= 1 && K <= D) fb.v2 += v2k;
 }
 
 template <int D, int R, int... K>
 __device__ __forceinline__ void recon_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
                                                const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
                                                double *__restrict__ face, long cell, long ncell, float *ratio,
-                                               std::integer_sequence<int, K...>)
+                                               FaceBounds &fb, std::integer_sequence<int, K...>)
 {
     // one pass per variable; the empty asm keeps each pass's LDS reads from
     // being hoisted into a single register-hungry prologue
     ((recon_var<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wt, ph, flags, face,
-                         cell, ncell, ratio)),
+                         cell, ncell, ratio, fb)),
      ...);
 }
 
@@ -173,7 +193,9 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     // entries, applied row by row with one compile-time pass per variable
     PhiRows<D> ph;
     ph.init(ref, gam);
-    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, ratio, std::make_integer_sequence<int, NV>{});
+    FaceBounds fb;
+    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, ratio, fb,
+                         std::make_integer_sequence<int, NV>{});
 
     // positivity limiter (section 4) on the cell's Riemann states
     double th_rho = 1.0, th_p = 1.0;
@@ -202,16 +224,22 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
         pmin *= 1.0 - lim.kappa;
         PhiInv<D> pi;
         pi.init(ref, gam);
-        // density scaling (eq. ppThetaRho), only the violated side of each bound
-#pragma unroll 1
-        for (int s = 0; s < NPTS; ++s) {
-            const double rs = face[(s * NV + 0) * g.ncell + cell];   // row 0 of Phi^-1 is e_0
-            if (rs < rmin) th_rho = fmin(th_rho, (ref[0] - rmin) / (ref[0] - rs));
-            else if (rs > rmax) th_rho = fmin(th_rho, (rmax - ref[0]) / (rs - ref[0]));
-        }
+        // density scaling (eq. ppThetaRho), only the violated side of each bound;
+        // the smallest ratio of a side is taken at its extreme point value (row
+        // 0 of Phi^-1 is e_0: the reconstructed density itself)
+        const double r0 = ref[0];
+        if (fb.rlo < rmin) th_rho = fmin(th_rho, (r0 - rmin) / (r0 - fb.rlo));
+        if (fb.rhi > rmax) th_rho = fmin(th_rho, (rmax - r0) / (fb.rhi - r0));
+        // pressure at a point, exactly: p = p~ + th dw_p - (gamma-1)/2 th^2 rho~^2 |dw_u|^2 / rho
+        // (dw: its increments in reconstruction variables).  The least dw_p and
+        // rho and the largest |dw_u|^2 bound every point from below; only a cell
+        // whose bound falls under pmin takes the per-point test and bisection.
+        const double rlo = r0 + th_rho * (fb.rlo - r0);
+        const double plow = pressure<D>(ref, gam) + th_rho * fb.plo -
+                            0.5 * (gam - 1.0) * th_rho * th_rho * r0 * r0 * fb.v2 * rcp64(rlo);
         // pressure scaling (eq. thetapRoot, eq. thetaP): 60 bisection steps
 #pragma unroll 1
-        for (int s = 0; s < NPTS; ++s) {
+        for (int s = 0; s < (rlo > 0.0 && plow >= pmin ? 0 : NPTS); ++s) {
             double w[NV], u[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
