@@ -38,6 +38,7 @@ typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int SB = 13;   // per-cell increment scale: max |delta| * 2^(SB - e) in [2^13, 2^14)
+constexpr double FLAT_REL = 0x1p-40;   // gate: increments below this fraction of the scale are flat
 
 // 3D tiles are 8 x 8 x 8 here: 1024 threads share one copy of the operand
 // tables in LDS (two lanes per cell), four waves per SIMD
@@ -261,7 +262,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                                           const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
                                           float *__restrict__ inc, uint32_t co, long ncell, bool active, int sw,
                                           const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out,
-                                          IncBounds &bnd)
+                                          const float (&wsc)[3], IncBounds &bnd)
 {
     using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
@@ -353,7 +354,11 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
             }
         }
         const float logit = gate_forward<D>(xb, lane, Wg, gvec);
-        use_weno = logit > thr;
+        // increments at rounding level (below 2^-40 of the variable's scale:
+        // density, sound speed or pressure) leave every stencil at W_c and
+        // WENO-AO at the linear value to rounding: smooth whatever the network
+        // says (its normalised inputs would be rounding noise)
+        use_weno = logit > thr && amax > (double)wsc[K == 0 ? 0 : (K <= D ? 1 : 2)];
         if (active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     }
     const uint32_t co4 = co * 4u;
@@ -466,10 +471,11 @@ __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::
                                                const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
                                                float *inc, uint32_t co, long ncell, bool active, int sw,
                                                const uint4 *Wg, const float *gvec, float thr, uint8_t *fl_out,
-                                               IncBounds &bnd, std::integer_sequence<int, K...>)
+                                               const float (&wsc)[3], IncBounds &bnd,
+                                               std::integer_sequence<int, K...>)
 {
     ((mixed_var<D, R, K, BF, GATE>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al,
-                                   ph, flags, inc, co, ncell, active, sw, Wg, gvec, thr, fl_out, bnd)),
+                                   ph, flags, inc, co, ncell, active, sw, Wg, gvec, thr, fl_out, wsc, bnd)),
      ...);
 }
 
@@ -548,8 +554,16 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     // every lane of the wave takes part in the matrix-core work; inactive and
     // non-physical cells compute on their (finite or not) data and store nothing
     IncBounds bnd;
+    // flatness thresholds: 2^-40 of the natural scales of the reconstruction
+    // variables (density, sound speed, pressure)
+    float wsc[3] = {(float)(FLAT_REL * ref[0]), 0.f, 0.f};
+    if constexpr (GATE) {
+        const double pc = pressure<D>(ref, gam);
+        wsc[1] = (float)(FLAT_REL * sqrt(fabs(gam * pc * ph.inv_rho)));
+        wsc[2] = (float)(FLAT_REL * pc);
+    }
     mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, flags, inc, co, g.ncell, active && ok, sw, Wg, gvec,
-                                   ga.thr, ga.flags_out, bnd, std::make_integer_sequence<int, NV>{});
+                                   ga.thr, ga.flags_out, wsc, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on) {

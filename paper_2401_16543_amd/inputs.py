@@ -20,7 +20,10 @@ averaging, so cell averages are those of the conserved variables.
   periodic slab with a small-integer normal and half-width ~ U(0.05, 0.15); inside
   a region rho is multiplied by r_rho and p by r_p, each log-uniform on
   [1, r_max] and inverted with probability 1/2.
-* isentropic_vortex(d): the vortex of the paper's convergence study on
+* density_wave(seed, d, M, vel, t): rho = 1 + 0.2 S_rho(x - vel t) with constant
+  velocity vel and p = 1, an exact solution of the Euler equations at every t
+  (for accuracy checks against the exact cell averages).
+* isentropic_vortex(gamma, t): the vortex of the paper's convergence study on
   [-10, 10]^2 (section 6.1), for validation runs.
 
 Cell averages use a tensor Gauss-Legendre rule (smooth fields) or sub-cell
@@ -48,6 +51,7 @@ class FieldSpec:
     domain_lo: float = 0.0
     domain_hi: float = 1.0
     vortex: bool = False
+    t: float = 0.0                  # vortex: advected by (1, 1) over time t
 
 
 _SLAB_NORMALS_2D = [(1, 0), (0, 1), (1, 1), (1, -1), (1, 2), (2, 1)]
@@ -103,8 +107,19 @@ def discontinuous(seed: int, d: int, n_disc: int, r_rho_max: float, r_p_max: flo
     return spec
 
 
-def isentropic_vortex(gamma: float = 1.4) -> FieldSpec:
-    return FieldSpec(d=2, modes=[], base=[], amp=[], domain_lo=-10.0, domain_hi=10.0, vortex=True)
+def density_wave(seed: int, d: int, M: int, vel, t: float = 0.0) -> FieldSpec:
+    rng = np.random.default_rng(seed)
+    k, a, phi = _draw_modes(rng, d, M)[0]
+    shift = 2.0 * np.pi * (k @ np.asarray(vel, dtype=np.float64)) * t     # sin(2 pi k.(x - vel t) + phi)
+    zero = (np.zeros((1, d), dtype=np.int64), np.zeros(1), np.zeros(1))
+    modes = [(k, a, phi - shift)] + [zero] * (d + 1)
+    base = [1.0] + [float(v) for v in vel] + [1.0]
+    amp = [0.2] + [0.0] * (d + 1)
+    return FieldSpec(d=d, modes=modes, base=base, amp=amp)
+
+
+def isentropic_vortex(gamma: float = 1.4, t: float = 0.0) -> FieldSpec:
+    return FieldSpec(d=2, modes=[], base=[], amp=[], domain_lo=-10.0, domain_hi=10.0, vortex=True, t=t)
 
 
 # ---------------------------------------------------------------------------
@@ -112,7 +127,9 @@ def _primitive(spec: FieldSpec, X: torch.Tensor, gamma: float):
     """Primitive variables [d + 2, P] at points X [P, d] (domain coordinates)."""
     d = spec.d
     if spec.vortex:
-        x, y = X[:, 0], X[:, 1]
+        # the vortex centre moves with the mean flow (1, 1); periodic image in [-10, 10)
+        x = torch.remainder(X[:, 0] - spec.t + 10.0, 20.0) - 10.0
+        y = torch.remainder(X[:, 1] - spec.t + 10.0, 20.0) - 10.0
         om = 5.0 * math.sqrt(2.0 * math.e) / (4.0 * math.pi) * torch.exp(-0.5 * (x * x + y * y))
         base = 1.0 + (1.0 - gamma) / 2.0 * om * om
         rho = base ** (1.0 / (gamma - 1.0))
