@@ -185,7 +185,10 @@ int kfvm_mlp_sizes(int dim, int *n_in, int *n_params);
 
 /* Enable the gate in the split-precision path: params is a device float32
  * vector (copied), a (variable, cell) takes WENO-AO when its logit exceeds
- * threshold.  params == NULL disables it.  Clears kfvm_set_flags. */
+ * threshold and its largest S0 increment exceeds 2^-40 of the variable's scale
+ * (density, sound speed or pressure of the cell; below that every stencil holds
+ * W_c to rounding and WENO-AO equals the linear value).  params == NULL
+ * disables it.  Clears kfvm_set_flags. */
 int kfvm_set_gate(kfvm_ctx *ctx, const float *params, float threshold);
 
 /* Copy the gate's decisions of the last reconstruction, flags[nvar][ncells]
