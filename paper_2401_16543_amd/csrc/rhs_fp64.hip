@@ -160,10 +160,14 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
 
     // tile + halo, periodic wrap (the ghost fill)
+    // a single conditional wrap reaches every halo index once the grid is at
+    // least a tile plus R wide along each axis; smaller grids take the modulo
+    const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
     for (int i = threadIdx.x; i < C::HN; i += C::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        const int gx = wrap_any(x0 + hx, g.n[0]), gy = wrap_any(y0 + hy, g.n[1]);
-        const int gz = D == 3 ? wrap_any(z0 + hz, g.n[2]) : 0;
+        const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
+        const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
+        const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
         const long cell = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
 #pragma unroll
         for (int v = 0; v < NV; ++v) tile[v][i] = U[v * g.ncell + cell];

@@ -123,21 +123,23 @@ __device__ __forceinline__ f16v mfma(uint4 a, uint4 b, f16v c)
 
 // hi/lo split of two scaled increments into packed 16-bit pairs: hi rounds to
 // nearest, the residual y - hi is exact in float32 and is rounded the same way,
-// so hi + lo keeps ~22 (fp16) or ~16 (bf16) significant bits of y.
+// so hi + lo keeps ~22 (fp16) or ~16 (bf16) significant bits of y.  Pairs go
+// through the packed float32 -> 16-bit conversions.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
 template <bool BF>
 __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uint32_t &lo)
 {
-    if constexpr (BF) {
-        const __bf16 ha = (__bf16)ya, hb = (__bf16)yb;
-        const __bf16 la = (__bf16)(ya - (float)ha), lb = (__bf16)(yb - (float)hb);
-        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
-        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | (uint32_t)__builtin_bit_cast(uint16_t, lb) << 16;
-    } else {
-        const _Float16 ha = (_Float16)ya, hb = (_Float16)yb;
-        const _Float16 la = (_Float16)(ya - (float)ha), lb = (_Float16)(yb - (float)hb);
-        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
-        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | (uint32_t)__builtin_bit_cast(uint16_t, lb) << 16;
-    }
+    using T2 = std::conditional_t<BF, b2v, h2v>;
+    const f2v y = {ya, yb};
+    const T2 h = __builtin_convertvector(y, T2);
+    const f2v hf = __builtin_convertvector(h, f2v);
+    const f2v r = {ya - hf.x, yb - hf.y};
+    const T2 l = __builtin_convertvector(r, T2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 // increment of variable K at contraction slots kA (lower half-wave) and kB
@@ -505,10 +507,14 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
     const double gam = g.gamma;
 
+    // a single conditional wrap reaches every halo index once the grid is at
+    // least a tile plus R wide along each axis; smaller grids take the modulo
+    const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
     for (int i = threadIdx.x; i < C::HN; i += M::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        const int gx = wrap_any(x0 + hx, g.n[0]), gy = wrap_any(y0 + hy, g.n[1]);
-        const int gz = D == 3 ? wrap_any(z0 + hz, g.n[2]) : 0;
+        const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
+        const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
+        const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
         const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
         double u[NV];
 #pragma unroll
