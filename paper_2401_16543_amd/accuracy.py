@@ -1,0 +1,96 @@
+"""Accuracy of the split-precision and gated paths on the named workloads.
+
+For each workload the FP64 GPU path (which matches the CPU oracle to ~1e-15 per
+right-hand side, see tests/test_gpu_parity.py) and the reduced-precision path
+run the workload's SSP-RK3 steps from the same initial state with the same dt
+sequence (CFL from the FP64 state); the L1 density difference (mean absolute
+cell-average difference) is reported.  With the learned gate, the
+misclassification rates against the WENO-AO labels (troubled iff
+1 - omega_0/gamma_0 > 0.5 in the FP64 reconstruction of the gated run's state)
+are measured at the first, middle and last step.
+
+    python -m paper_2401_16543_amd.accuracy [workload ...]
+
+Prints one JSON line per workload.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import time
+
+import torch
+
+from . import gate as gate_mod
+from . import inputs, kfvm
+
+PLANS = {
+    "2d_smooth_64": dict(paths=["split_f16"], gate=False),
+    "2d_jumps_1024": dict(paths=["split_bf16", "split_f16"], gate=False),
+    "3d_smooth_256": dict(paths=["split_f16", "split_f16+gate"], gate=True),
+    "2d_jumps_2048": dict(paths=["split_f16+gate", "split_f16"], gate=True),
+    "3d_jumps_384_r3": dict(paths=[], gate=False),
+}
+
+
+def _misclassification(dev, U, n_in):
+    """(false-smooth rate, false-troubled rate, flagged fraction) of the gate's
+    decisions on state U against the FP64 WENO-AO labels."""
+    dev.rhs(U)
+    flags = dev.get_flags().bool()
+    _, ratio = dev.gate_samples(U)
+    troubled = (1.0 - ratio) > gate_mod.LABEL_CUT
+    fs = float((troubled & ~flags).sum()) / max(1, int(troubled.sum()))
+    ft = float((~troubled & flags).sum()) / max(1, int((~troubled).sum()))
+    return fs, ft, float(flags.float().mean())
+
+
+def run(name: str, log=print):
+    cfg = inputs.WORKLOADS[name]
+    plan = PLANS[name]
+    U0, cfg = inputs.config_state(name, device="cuda")
+    d, n, R, gamma, steps = cfg["d"], cfg["n"], cfg["R"], cfg["gamma"], cfg["steps"]
+    ref = kfvm.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
+    runs = {}
+    for path in plan["paths"]:
+        dev = kfvm.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
+        dev.set_precision(path.split("+")[0])
+        if path.endswith("+gate"):
+            p, thr, _ = gate_mod.load(d)
+            dev.set_gate(torch.from_numpy(p).cuda(), thr)
+        runs[path] = [dev, U0.clone(), []]
+    Ur = U0.clone()
+    t0 = time.time()
+    mis_at = {0, steps // 2, steps - 1}
+    for it in range(steps):
+        dt = ref.cfl_dt(Ur, cfg["cfl"])
+        for path, (dev, U, mis) in runs.items():
+            if path.endswith("+gate") and it in mis_at:
+                mis.append((it,) + _misclassification(dev, U, None))
+            dev.step(U, dt)
+        ref.step(Ur, dt)
+    torch.cuda.synchronize()
+    out = {"workload": name, "grid": [n] * d, "R": R, "steps": steps, "seconds": round(time.time() - t0, 1),
+           "status_fp64": ref.status()}
+    for path, (dev, U, mis) in runs.items():
+        out[path] = {"l1_rho_vs_fp64": float((U[0] - Ur[0]).abs().mean()),
+                     "max_rel_rho_vs_fp64": float((U[0] - Ur[0]).abs().max() / Ur[0].abs().max()),
+                     "status": dev.status()}
+        if mis:
+            out[path]["misclassification"] = [dict(step=m[0], false_smooth=m[1], false_troubled=m[2], flagged=m[3])
+                                              for m in mis]
+        dev.close()
+    out["rho_range"] = [float(Ur[0].min()), float(Ur[0].max())]
+    ref.close()
+    log(json.dumps(out))
+    return out
+
+
+def main():
+    names = sys.argv[1:] or list(PLANS)
+    for nm in names:
+        run(nm, log=lambda s: print(s, flush=True))
+
+
+if __name__ == "__main__":
+    main()
