@@ -124,7 +124,7 @@ def test_ssp_rk3_trajectory_2d_64(K, oracle_mod):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("name,nsample", [("2d_jumps_1024", 600), ("3d_smooth_256", 160)])
+@pytest.mark.parametrize("name,nsample", [("2d_jumps_1024", 600), ("3d_smooth_256", 160), ("3d_jumps_384_r3", 60)])
 def test_full_size_sampled(K, oracle_mod, name, nsample):
     """Full-size workloads: the GPU RHS over the whole grid (the benchmark's
     launch configuration) against the oracle at sampled cells, plus conservation."""
