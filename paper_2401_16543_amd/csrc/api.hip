@@ -215,7 +215,8 @@ int prepare_mixed(kfvm_ctx *c, int mode)
     std::vector<uint16_t> full, lin;
     if (c->dim == 2 && c->R == 2) build_operands<2, 2>(c->host_tables.data(), bf16, sw, full, lin);
     else if (c->dim == 2 && c->R == 3) build_operands<2, 3>(c->host_tables.data(), bf16, sw, full, lin);
-    else build_operands<3, 2>(c->host_tables.data(), bf16, sw, full, lin);
+    else if (c->dim == 3 && c->R == 2) build_operands<3, 2>(c->host_tables.data(), bf16, sw, full, lin);
+    else build_operands<3, 3>(c->host_tables.data(), bf16, sw, full, lin);
     if (!c->d_mix_full) {
         int rc = alloc(c, (void **)&c->d_mix_full, full.size() * 2);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_mix_lin, lin.size() * 2);
@@ -391,7 +392,7 @@ int kfvm_set_precision(kfvm_ctx *c, int mode)
         return fail(c, KFVM_ERR_ARG, "unknown precision mode");
     if (mode != KFVM_FP64) {
         if (!kfvm::mixed_supported(c->dim, c->R))
-            return fail(c, KFVM_ERR_ARG, "split precision is not available for 3D R = 3");
+            return fail(c, KFVM_ERR_ARG, "split precision is not available for this dimension and order");
         const int rc = prepare_mixed(c, mode);
         if (rc != KFVM_OK) return rc;
     }
@@ -484,7 +485,7 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
         c->gate_on = 0;
         return KFVM_OK;
     }
-    if (!kfvm::mixed_supported(c->dim, c->R)) return fail(c, KFVM_ERR_ARG, "the gate needs the split-precision path");
+    if (!kfvm::gate_supported(c->dim, c->R)) return fail(c, KFVM_ERR_ARG, "the gate is not available for 3D order 7");
     const int nin = kfvm::mlp_n_in(c->dim), P = kfvm::mlp_n_params(c->dim), H = 32;
     std::vector<float> p(P);
     HIP_TRY(c, hipMemcpy(p.data(), params, sizeof(float) * P, hipMemcpyDeviceToHost));

@@ -70,6 +70,7 @@ struct GateArgs {
 };
 
 bool mixed_supported(int dim, int R);
+bool gate_supported(int dim, int R);     // the learned gate runs in the split-precision kernels of (dim, R)
 int gate_operand_slots(int dim);
 int gate_slot_input(int dim, int k);   // network input fed by W1 operand column k, or -1
 int gate_w1_exp(int dim);              // power of two folded into the W1 operand

@@ -40,10 +40,10 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 constexpr int SB = 13;   // per-cell increment scale: max |delta| * 2^(SB - e) in [2^13, 2^14)
 constexpr double FLAT_REL = 0x1p-40;   // gate: increments below this fraction of the scale are flat
 
-// 3D tiles are 8 x 8 x 8 here: 1024 threads share one copy of the operand
-// tables in LDS (two lanes per cell), four waves per SIMD
+// 3D tiles are 8 x 8 x 8 here (8 x 8 x 4 for R = 3): the threads of a block
+// (two lanes per cell) share one copy of the operand tables in LDS
 template <int D, int R>
-using MCfg = Cfg<D, R, (D == 3 ? 8 : 1)>;
+using MCfg = Cfg<D, R, (D == 3 ? (R == 2 ? 8 : 4) : 1)>;
 
 template <int D, int R>
 struct MixCfg {
@@ -58,6 +58,9 @@ struct MixCfg {
     static constexpr int A_LIN = NTL * KS * 2 * 64;
     static constexpr int NT = 2 * MCfg<D, R>::NT;                // two lanes per cell
 };
+
+// the 3D R = 3 operand tables exceed LDS and are streamed through it
+constexpr bool streamed_tables(int dim, int R) { return dim == 3 && R == 3; }
 
 // ---------------------------------------------------- half-wave exchange ---
 // v_permlane32_swap trades the upper half of its first register with the lower
@@ -481,36 +484,20 @@ __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::
      ...);
 }
 
-template <int D, int R, bool BF, bool GATE>
-__global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
-    const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
-    float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
-    Geom g, Limiter lim, int sw, GateArgs ga)
+// Tile of conserved averages plus its R-cell halo (periodic wrap = ghost fill)
+// into LDS; with the limiter on, also each tile cell's pressure (-1 where the
+// average is not admissible) for the neighbourhood bounds.
+template <int D, int R, int NTHR, typename PT>
+__device__ __forceinline__ void load_tile(const double *__restrict__ U, const Geom &g, const Limiter &lim, int x0,
+                                          int y0, int z0, double (*tile)[MCfg<D, R>::HN], PT *ptile)
 {
     using C = MCfg<D, R>;
-    using M = MixCfg<D, R>;
-    using S = typename C::S;
-    constexpr int NV = C::NV, NPTS = S::NPTS;
-    __shared__ double tile[NV][C::HN];
-    __shared__ double ptile[C::HN];      // pressure of each tile cell, -1 where not admissible
-    __shared__ uint4 As[M::A_FULL];
-    __shared__ uint4 Al[M::A_LIN];
-    __shared__ uint4 Wg[GATE ? GateShape<D>::SLOTS : 1];
-    __shared__ __align__(16) float gvec[GATE ? 100 : 4];
-
-    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
-    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
-    const long nblk = (long)nbx * nby * nbz;
-    const long tb = xcd_tile(blockIdx.x, nblk);
-    if (tb >= nblk) return;
-    const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
-    const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+    constexpr int NV = C::NV;
     const double gam = g.gamma;
-
     // a single conditional wrap reaches every halo index once the grid is at
     // least a tile plus R wide along each axis; smaller grids take the modulo
     const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
-    for (int i = threadIdx.x; i < C::HN; i += M::NT) {
+    for (int i = threadIdx.x; i < C::HN; i += NTHR) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
         const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
         const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
@@ -530,9 +517,117 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
 #pragma unroll
             for (int a = 0; a < D; ++a) mm += u[1 + a] * u[1 + a];
             const double p = (gam - 1.0) * (u[D + 1] - 0.5 * mm * rcp64(u[0]));
-            ptile[i] = fin && u[0] > 0.0 && p > 0.0 ? p : -1.0;
+            ptile[i] = (PT)(fin && u[0] > 0.0 && p > 0.0 ? p : -1.0);
         }
     }
+}
+
+// Positivity limiter (section 4) of one cell from the running bounds of its
+// stored face-point increments; both half-waves of the cell call it and get
+// the same factors.
+template <int D, int R, typename PT>
+__device__ __forceinline__ void limiter_factors(const double (*tile)[MCfg<D, R>::HN], const PT *ptile, int lc, int hf,
+                                                const double *ref, bool active, bool ok, const IncBounds &bnd,
+                                                const Limiter &lim, const Geom &g, const float *__restrict__ inc,
+                                                long cell, int *__restrict__ err, double &th_rho, double &th_p)
+{
+    using C = MCfg<D, R>;
+    constexpr int NV = D + 2, NPTS = C::S::NPTS;
+    const double gam = g.gamma;
+    th_rho = 1.0;
+    th_p = 1.0;
+    // bounds over the 3^d block; the two half-waves take alternate neighbours
+    double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+    constexpr int NB = D == 3 ? 27 : 9;
+#pragma unroll
+    for (int j = 0; j < (NB + 1) / 2; ++j) {
+        const int nA = 2 * j, nB = 2 * j + 1 < NB ? 2 * j + 1 : 2 * j;
+        const int oA = nA % 3 - 1 + C::HX * ((nA / 3) % 3 - 1 + C::HY * (D == 3 ? nA / 9 - 1 : 0));
+        const int oB = nB % 3 - 1 + C::HX * ((nB / 3) % 3 - 1 + C::HY * (D == 3 ? nB / 9 - 1 : 0));
+        const int o = lc + (hf ? oB : oA);
+        const double r = tile[0][o];
+        rmax = fmax(rmax, r);
+        rmin = fmin(rmin, r);
+        pmin = fmin(pmin, (double)ptile[o]);
+    }
+    rmax = pair_max(rmax);
+    rmin = pair_min(rmin);
+    pmin = pair_min(pmin);
+    if (!(pmin > 0.0) && active) *err = ERR_NONPHYSICAL;   // a neighbour is not admissible
+    rmax *= 1.0 + lim.kappa;
+    rmin *= 1.0 - lim.kappa;
+    pmin *= 1.0 - lim.kappa;
+    bool exact = false;
+    if (active && ok) {
+        // density scaling (eq. ppThetaRho) from the extreme point values: the
+        // smallest ratio of each violated side is taken at its extreme point
+        const double r0 = ref[0];
+        const double rs_lo = r0 + (double)bnd.rlo, rs_hi = r0 + (double)bnd.rhi;
+        if (rs_lo < rmin) th_rho = fmin(th_rho, (r0 - rmin) / (r0 - rs_lo));
+        if (rs_hi > rmax) th_rho = fmin(th_rho, (rmax - r0) / (rs_hi - r0));
+        // pressure at a point, exactly: p = p~ + th dw_p - (gamma-1)/2 th^2 rho~^2 |dw_u|^2 / rho
+        // (dw: its increments in reconstruction variables).  With the least
+        // dw_p and rho and the largest |dw_u|^2 this bounds every point from
+        // below; only a cell whose bound falls under pmin takes the per-point
+        // test and bisection (eq. thetapRoot, eq. thetaP).
+        const double rlo = r0 + th_rho * (double)bnd.rlo;
+        const double plow = pressure<D>(ref, gam) + th_rho * (double)bnd.plo -
+                            0.5 * (gam - 1.0) * th_rho * th_rho * r0 * r0 * (double)bnd.v2 * rcp64(rlo);
+        exact = !(rlo > 0.0 && plow >= pmin);
+    }
+    if (exact) {
+        PhiInv<D> pi;
+        pi.init(ref, gam);
+        // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
+#pragma unroll 1
+        for (int tau = hf; tau < NPTS; tau += 2) {
+            double w[NV], d[NV], u[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)tau * NV + v) * g.ncell + cell];
+            pi.apply(w, d);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
+            if (pressure<D>(u, gam) >= pmin) continue;
+            double lo = 0.0, hi = 1.0;
+#pragma unroll 1
+            for (int it = 0; it < 60; ++it) {
+                const double m = 0.5 * (lo + hi);
+                double um[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) um[v] = ref[v] + m * th_rho * d[v];
+                if (pressure<D>(um, gam) >= pmin) lo = m; else hi = m;
+            }
+            th_p = fmin(th_p, lo);
+        }
+    }
+    th_p = pair_min(th_p);
+}
+
+template <int D, int R, bool BF, bool GATE>
+__global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
+    const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
+    float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
+    Geom g, Limiter lim, int sw, GateArgs ga)
+{
+    using C = MCfg<D, R>;
+    using M = MixCfg<D, R>;
+    constexpr int NV = C::NV;
+    __shared__ double tile[NV][C::HN];
+    __shared__ double ptile[C::HN];      // pressure of each tile cell, -1 where not admissible
+    __shared__ uint4 As[M::A_FULL];
+    __shared__ uint4 Al[M::A_LIN];
+    __shared__ uint4 Wg[GATE ? GateShape<D>::SLOTS : 1];
+    __shared__ __align__(16) float gvec[GATE ? 100 : 4];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long tb = xcd_tile(blockIdx.x, nblk);
+    if (tb >= nblk) return;
+    const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
+    const double gam = g.gamma;
+
+    load_tile<D, R, M::NT>(U, g, lim, bx * C::TX - R, by * C::TY - R, D == 3 ? bz * C::TZ - R : 0, tile, ptile);
     for (int i = threadIdx.x; i < M::A_FULL; i += M::NT) As[i] = Afull[i];
     for (int i = threadIdx.x; i < M::A_LIN; i += M::NT) Al[i] = Alin[i];
     if constexpr (GATE) {
@@ -572,73 +667,295 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
                                    ga.thr, ga.flags_out, wsc, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
-    if (lim.on) {
-        // bounds over the 3^d block; the two half-waves take alternate neighbours
-        double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
-        constexpr int NB = D == 3 ? 27 : 9;
+    if (lim.on)
+        limiter_factors<D, R>(tile, ptile, lc, hf, ref, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
+    if (active && hf == 0) {
+        theta[cell] = th_rho;
+        theta[g.ncell + cell] = th_p;
+    }
+}
+
+// --------------------------------------------------- streamed tables (3D R3) ---
+// The interleaved operand table of the 3D R = 3 reconstruction (19 tiles of 8
+// k-steps, ~311 KB) does not fit LDS.  It stays in global memory (L2-resident:
+// every block reads the same bytes) and passes through a double-buffered LDS
+// window of two tiles, loaded straight into LDS (global_load_lds_dwordx4)
+// while the previous pair is in use.  Per variable the block first agrees
+// whether any of its waves needs WENO-AO; if none does, only the S0 face-point
+// table (two tiles) passes through.
+template <int D, int R>
+struct StreamCfg {
+    using M = MixCfg<D, R>;
+    static constexpr int PH = 2;                              // tiles per phase
+    static constexpr int TSL = M::KS * 2 * 64;                // 16-byte slots per tile (hi and lo)
+    static constexpr int NPD = (M::NTF - M::TD_BEGIN + PH - 1) / PH;   // derivative-row phases
+    static constexpr int NPP = (M::TP_END + PH - 1) / PH;     // point-row phases
+};
+
+// queue tiles [t0, min(t0 + PH, tend)) of table A into LDS buffer dst; every
+// wave copies whole 64-slot rows, one 16-byte slot per lane
+template <int D, int R>
+__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ A, int t0, int tend, uint4 *dst)
+{
+    using SC = StreamCfg<D, R>;
+    constexpr int NW = MixCfg<D, R>::NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = (tend - t0 < SC::PH ? tend - t0 : SC::PH);
+    const int rows = n * SC::TSL / 64;
+    typedef __attribute__((address_space(1))) void *gptr;
+    typedef __attribute__((address_space(3))) void *lptr;
+    for (int r = wave; r < rows; r += NW)
+        __builtin_amdgcn_global_load_lds((gptr)(A + (long)t0 * SC::TSL + r * 64 + lane), (lptr)(dst + r * 64), 16, 0,
+                                         0);
+}
+
+// this wave's own direct-to-LDS loads (and every other memory operation) done,
+// then every wave's
+__device__ __forceinline__ void stream_wait()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+template <int D, int R, int K, bool BF>
+__device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>::HN], int lc, int lane,
+                                                 const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
+                                                 uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
+                                                 const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                                 float *__restrict__ inc, uint32_t co, long ncell, bool active,
+                                                 int sw, IncBounds &bnd)
+{
+    using C = MCfg<D, R>;
+    using M = MixCfg<D, R>;
+    using SC = StreamCfg<D, R>;
+    using S = typename C::S;
+    constexpr int NV = C::NV, NST = S::NST, NPTS = S::NPTS, NROWS = S::NROWS, KS = M::KS;
+    const int hf = lane >> 5;
+    const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
+
+    // increments over this lane's slots 16 ks + 8 hf + i, rounded to float32
+    // once (scaling by a power of two afterwards is exact)
+    float ys[KS][8];
+    float amax = 0.f;
+    int lcc = lc;
 #pragma unroll
-        for (int j = 0; j < (NB + 1) / 2; ++j) {
-            const int nA = 2 * j, nB = 2 * j + 1 < NB ? 2 * j + 1 : 2 * j;
-            const int oA = nA % 3 - 1 + C::HX * ((nA / 3) % 3 - 1 + C::HY * (D == 3 ? nA / 9 - 1 : 0));
-            const int oB = nB % 3 - 1 + C::HX * ((nB / 3) % 3 - 1 + C::HY * (D == 3 ? nB / 9 - 1 : 0));
-            const int o = lc + (hf ? oB : oA);
-            const double r = tile[0][o];
-            rmax = fmax(rmax, r);
-            rmin = fmin(rmin, r);
-            pmin = fmin(pmin, ptile[o]);
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            ys[ks][i] = (float)slot_increment<D, R, K>(tile, lcc, hf, 16 * ks + i, 16 * ks + 8 + i, ph, Wc);
+            asm volatile("" : "+v"(ys[ks][i]));
+            amax = fmaxf(amax, fabsf(ys[ks][i]));
         }
-        rmax = pair_max(rmax);
-        rmin = pair_min(rmin);
-        pmin = pair_min(pmin);
-        if (!(pmin > 0.0) && active) *err = ERR_NONPHYSICAL;   // a neighbour is not admissible
-        rmax *= 1.0 + lim.kappa;
-        rmin *= 1.0 - lim.kappa;
-        pmin *= 1.0 - lim.kappa;
-        bool exact = false;
-        if (active && ok) {
-            // density scaling (eq. ppThetaRho) from the extreme point values: the
-            // smallest ratio of each violated side is taken at its extreme point
-            const double r0 = ref[0];
-            const double rs_lo = r0 + (double)bnd.rlo, rs_hi = r0 + (double)bnd.rhi;
-            if (rs_lo < rmin) th_rho = fmin(th_rho, (r0 - rmin) / (r0 - rs_lo));
-            if (rs_hi > rmax) th_rho = fmin(th_rho, (rmax - r0) / (rs_hi - r0));
-            // pressure at a point, exactly: p = p~ + th dw_p - (gamma-1)/2 th^2 rho~^2 |dw_u|^2 / rho
-            // (dw: its increments in reconstruction variables).  With the least
-            // dw_p and rho and the largest |dw_u|^2 this bounds every point from
-            // below; only a cell whose bound falls under pmin takes the per-point
-            // test and bisection (eq. thetapRoot, eq. thetaP).
-            const double rlo = r0 + th_rho * (double)bnd.rlo;
-            const double plow = ptile[lc] + th_rho * (double)bnd.plo -
-                                0.5 * (gam - 1.0) * th_rho * th_rho * r0 * r0 * (double)bnd.v2 * rcp64(rlo);
-            exact = !(rlo > 0.0 && plow >= pmin);
-        }
-        if (exact) {
-            PhiInv<D> pi;
-            pi.init(ref, gam);
-            // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
+        asm volatile("" : "+v"(lcc) : "v"(ys[ks][7]));
+    }
+    amax = pair_max(amax);
+    int ex = 0;
+    if (amax > 0.f) frexpf(amax, &ex);         // amax in [2^(ex-1), 2^ex)
+    const int e = ex - 1;
+    const int ue = e - SB - sw;                  // accumulator units: value = acc * 2^ue
+    uint4 bh[KS], bl[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            split_pair<BF>(ldexpf(ys[ks][2 * i], SB - e), ldexpf(ys[ks][2 * i + 1], SB - e), h[i], l[i]);
+        bh[ks] = make_uint4(h[0], h[1], h[2], h[3]);
+        bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
+    }
+
+    const bool use_weno = flags ? at4(flags, (long)K * ncell, co) != 0 : true;
+    const uint32_t co4 = co * 4u;
+    float v2k = 0.f;
+    const bool wave_weno = __any(use_weno && active);
+    if (__syncthreads_or(wave_weno)) {
+        float bp[4] = {0.f, 0.f, 0.f, 0.f};
+        float cm[4] = {hf == 0 ? 1.f : 0.f, 0.f, 0.f, 0.f};
+        constexpr int NPH = SC::NPD + SC::NPP;
+        stream_tiles<D, R>(Afull, M::TD_BEGIN, M::NTF, buf[0]);
 #pragma unroll 1
-            for (int tau = hf; tau < NPTS; tau += 2) {
-                double w[NV], d[NV], u[NV];
+        for (int p = 0; p < NPH; ++p) {
+            stream_wait();
+            if (p + 1 < NPH) {
+                const int q = p + 1;
+                if (q < SC::NPD) stream_tiles<D, R>(Afull, M::TD_BEGIN + SC::PH * q, M::NTF, buf[q & 1]);
+                else stream_tiles<D, R>(Afull, SC::PH * (q - SC::NPD), M::TP_END, buf[q & 1]);
+            }
+            const uint4 *As = buf[p & 1];
+            if (p < SC::NPD) {
+                // smoothness indicators: derivative tiles of this phase
+                if (wave_weno) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)tau * NV + v) * g.ncell + cell];
-                pi.apply(w, d);
+                    for (int tt = 0; tt < SC::PH; ++tt) {
+                        const int t = M::TD_BEGIN + SC::PH * p + tt;
+                        if (t < M::NTF) {
+                            f16v acc = {};
 #pragma unroll
-                for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
-                if (pressure<D>(u, gam) >= pmin) continue;
-                double lo = 0.0, hi = 1.0;
-#pragma unroll 1
-                for (int it = 0; it < 60; ++it) {
-                    const double m = 0.5 * (lo + hi);
-                    double um[NV];
+                            for (int ks = 0; ks < KS; ++ks) {
+                                const uint4 ah = As[((tt * KS + ks) * 2 + 0) * 64 + lane];
+                                const uint4 al = As[((tt * KS + ks) * 2 + 1) * 64 + lane];
+                                acc = mfma<BF>(ah, bh[ks], acc);
+                                acc = mfma<BF>(ah, bl[ks], acc);
+                                acc = mfma<BF>(al, bh[ks], acc);
+                            }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) um[v] = ref[v] + m * th_rho * d[v];
-                    if (pressure<D>(um, gam) >= pmin) lo = m; else hi = m;
+                            for (int j = 0; j < 16; ++j) {
+                                const int tau = 4 * t + j / 4;
+                                if (tau >= NPTS && tau < NROWS) bp[j % 4] += acc[j] * acc[j];
+                            }
+                        }
+                    }
                 }
-                th_p = fmin(th_p, lo);
+                if (p == SC::NPD - 1 && wave_weno) {
+                    // nonlinear weights (eq. nlinWts) in FP64 and WENO-AO
+                    // coefficients (eq. wenoAOrec); linear cells keep stencil 0
+                    double om[4], part = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int q = 4 * hf + i;
+                        const double beta = ldexp((double)bp[i], 2 * ue);
+                        om[i] = q < NST ? lin_w<D>(q) * rcp64(beta * beta + EPS_WENO) : 0.0;
+                        part += om[i];
+                    }
+                    const double inv = rcp64(pair_sum(part));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) om[i] *= inv;
+                    const double om0 = lower_half(om[0]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int q = 4 * hf + i;
+                        double cq = q == 0 ? om0 * inv_lin0<D>() : (q < NST ? om[i] - om0 * lin_ratio<D>(q) : 0.0);
+                        if (!use_weno) cq = q == 0 ? 1.0 : 0.0;
+                        cm[i] = (float)cq;
+                    }
+                }
+            } else {
+                // blended face-point increments of this phase's point tiles
+#pragma unroll
+                for (int tt = 0; tt < SC::PH; ++tt) {
+                    const int t = SC::PH * (p - SC::NPD) + tt;
+                    if (t < M::TP_END) {
+                        f16v acc = {};
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const uint4 ah = As[((tt * KS + ks) * 2 + 0) * 64 + lane];
+                            const uint4 al = As[((tt * KS + ks) * 2 + 1) * 64 + lane];
+                            acc = mfma<BF>(ah, bh[ks], acc);
+                            acc = mfma<BF>(ah, bl[ks], acc);
+                            acc = mfma<BF>(al, bh[ks], acc);
+                        }
+#pragma unroll
+                        for (int gq = 0; gq < 4; ++gq) {
+                            const int tau = 4 * t + gq;
+                            if (tau < NPTS) {
+                                float part4 = 0.f;
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) part4 += cm[i] * acc[4 * gq + i];
+                                const float val = ldexpf(pair_sum(part4), ue);
+                                note_increment<D, K>(bnd, val, v2k);
+                                if ((tau & 1) == hf && active) at4(inc, 4 * ((long)tau * NV + K) * ncell, co4) = val;
+                            }
+                        }
+                    }
+                }
             }
         }
-        th_p = pair_min(th_p);
+    } else {
+        // no wave of the block needs WENO-AO for this variable: S0 face rows only
+        stream_tiles<D, R>(Alin, 0, M::NTL, buf[0]);
+        stream_wait();
+        const uint4 *Al = buf[0];
+#pragma unroll
+        for (int t = 0; t < M::NTL; ++t) {
+            f16v acc = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const uint4 ah = Al[((t * KS + ks) * 2 + 0) * 64 + lane];
+                const uint4 al = Al[((t * KS + ks) * 2 + 1) * 64 + lane];
+                acc = mfma<BF>(ah, bh[ks], acc);
+                acc = mfma<BF>(ah, bl[ks], acc);
+                acc = mfma<BF>(al, bh[ks], acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int T0 = 32 * t + 8 * (j / 4) + j % 4;
+                float vlo, vhi;
+                halves(ldexpf(acc[j], ue), vlo, vhi);
+                if (T0 < NPTS) note_increment<D, K>(bnd, vlo, v2k);
+                if (T0 + 4 < NPTS) note_increment<D, K>(bnd, vhi, v2k);
+                if (active && hf == (T0 & 1)) {
+                    if (T0 < NPTS) at4(inc, 4 * ((long)T0 * NV + K) * ncell, co4) = vlo;
+                    if (T0 + 4 < NPTS) at4(inc, 4 * ((long)(T0 + 4) * NV + K) * ncell, co4) = vhi;
+                }
+            }
+        }
     }
+    // the buffers are free again only when every wave is done with them
+    __syncthreads();
+    if constexpr (K >= 1 && K <= D) bnd.v2 += v2k;
+}
+
+template <int D, int R, bool BF, int... K>
+__device__ __forceinline__ void mixed_all_vars_stream(const double (*tile)[MCfg<D, R>::HN], int lc, int lane,
+                                                      const uint4 *Afull, const uint4 *Alin,
+                                                      uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
+                                                      const PhiRows<D> &ph, const uint8_t *flags, float *inc,
+                                                      uint32_t co, long ncell, bool active, int sw, IncBounds &bnd,
+                                                      std::integer_sequence<int, K...>)
+{
+    ((mixed_var_stream<D, R, K, BF>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, Afull,
+                                    Alin, buf, ph, flags, inc, co, ncell, active, sw, bnd)),
+     ...);
+}
+
+template <int D, int R, bool BF>
+__global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
+    const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
+    float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
+    Geom g, Limiter lim, int sw)
+{
+    using C = MCfg<D, R>;
+    using M = MixCfg<D, R>;
+    using SC = StreamCfg<D, R>;
+    constexpr int NV = C::NV;
+    __shared__ double tile[NV][C::HN];
+    __shared__ float ptile[C::HN];       // pressure of each tile cell, -1 where not admissible
+    __shared__ uint4 buf[2][SC::PH * SC::TSL];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long tb = xcd_tile(blockIdx.x, nblk);
+    if (tb >= nblk) return;
+    const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
+    const double gam = g.gamma;
+
+    load_tile<D, R, M::NT>(U, g, lim, bx * C::TX - R, by * C::TY - R, D == 3 ? bz * C::TZ - R : 0, tile, ptile);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;
+    const int ci = wave * 32 + (lane & 31);
+    const int tx = ci % C::TX, ty = (ci / C::TX) % C::TY, tz = ci / (C::TX * C::TY);
+    const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
+    const bool active = cx < g.n[0] && cy < g.n[1] && (D == 2 || cz < g.n[2]);
+    const long cell = active ? cx + (long)g.n[0] * (cy + (long)g.n[1] * cz) : 0;
+    const uint32_t co = (uint32_t)cell;
+    const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
+
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
+    const bool ok = admissible<D>(ref, gam);
+    if (!ok && active) *err = ERR_NONPHYSICAL;
+    PhiRows<D> ph;
+    ph.init(ref, gam);
+    IncBounds bnd;
+    mixed_all_vars_stream<D, R, BF>(tile, lc, lane, Afull, Alin, buf, ph, flags, inc, co, g.ncell, active && ok, sw,
+                                    bnd, std::make_integer_sequence<int, NV>{});
+
+    double th_rho = 1.0, th_p = 1.0;
+    if (lim.on)
+        limiter_factors<D, R>(tile, ptile, lc, hf, ref, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
     if (active && hf == 0) {
         theta[cell] = th_rho;
         theta[g.ncell + cell] = th_p;
@@ -761,12 +1078,18 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;
     mark(KT_RECON, 1);
-    if (ga.w)
-        hipLaunchKernelGGL((k_recon_mixed<D, R, BF, true>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
-                           t.lin, w.inc32, w.theta, w.err, (const uint8_t *)nullptr, g, lim, t.sw, ga);
-    else
-        hipLaunchKernelGGL((k_recon_mixed<D, R, BF, false>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
-                           t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw, ga);
+    if constexpr (streamed_tables(D, R)) {
+        if (ga.w) return hipErrorInvalidValue;   // no gate on the streamed path
+        hipLaunchKernelGGL((k_recon_mixed_stream<D, R, BF>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
+                           t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw);
+    } else {
+        if (ga.w)
+            hipLaunchKernelGGL((k_recon_mixed<D, R, BF, true>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin,
+                               t.full, t.lin, w.inc32, w.theta, w.err, (const uint8_t *)nullptr, g, lim, t.sw, ga);
+        else
+            hipLaunchKernelGGL((k_recon_mixed<D, R, BF, false>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin,
+                               t.full, t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw, ga);
+    }
     mark(KT_RECON, 0);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     if (states) {
@@ -785,7 +1108,9 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
 
 }  // namespace
 
-bool mixed_supported(int dim, int R) { return !(dim == 3 && R == 3); }
+bool mixed_supported(int dim, int R) { return (dim == 2 || dim == 3) && (R == 2 || R == 3); }
+
+bool gate_supported(int dim, int R) { return !streamed_tables(dim, R); }
 
 int gate_operand_slots(int dim) { return dim == 2 ? GateShape<2>::SLOTS : GateShape<3>::SLOTS; }
 
@@ -803,6 +1128,7 @@ int mixed_operand_slots(int dim, int R, int which)
     if (dim == 2 && R == 2) KF_SLOTS(2, 2);
     if (dim == 2 && R == 3) KF_SLOTS(2, 3);
     if (dim == 3 && R == 2) KF_SLOTS(3, 2);
+    if (dim == 3 && R == 3) KF_SLOTS(3, 3);
 #undef KF_SLOTS
     return -1;
 }
@@ -817,6 +1143,7 @@ hipError_t launch_rhs_mixed(int dim, int R, bool bf16, const Geom &g, const MixT
     if (dim == 2 && R == 2) KF_MIX(2, 2);
     if (dim == 2 && R == 3) KF_MIX(2, 3);
     if (dim == 3 && R == 2) KF_MIX(3, 2);
+    if (dim == 3 && R == 3) KF_MIX(3, 3);
 #undef KF_MIX
     return hipErrorInvalidValue;
 }

@@ -131,7 +131,8 @@ constexpr bool centre_is_middle()
     constexpr int c = Stencil<D, R>::N0 / 2;
     return s.off[c][0] == 0 && s.off[c][1] == 0 && s.off[c][2] == 0;
 }
-static_assert(centre_is_middle<2, 2>() && centre_is_middle<2, 3>() && centre_is_middle<3, 2>(),
+static_assert(centre_is_middle<2, 2>() && centre_is_middle<2, 3>() && centre_is_middle<3, 2>() &&
+                  centre_is_middle<3, 3>(),
               "S0 centre must sit in the middle of the lexicographic order");
 
 // linear weights of section 3.2 (gamma_hi = gamma_lo = 0.8)

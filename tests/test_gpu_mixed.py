@@ -40,7 +40,8 @@ def _U(kind, d, n, seed):
 
 # (d, R, n, kind, mode, rhs tolerance, states tolerance): a hi/lo pair of FP16
 # values carries ~22 significant bits (BF16: ~16) of each operand, relative to
-# the largest increment of the cell
+# the largest increment of the cell; the 122-point rows of 3D R = 3 cancel more
+# (sum |w delta| over |sum w delta|), so their smooth-data bound is wider
 MIXED = [
     (2, 2, (64, 64), "smooth", "split_f16", 2e-6, 2e-7),
     (2, 2, (37, 29), "jumps", "split_f16", 2e-5, 2e-6),
@@ -49,6 +50,9 @@ MIXED = [
     (3, 2, (16, 16, 16), "smooth", "split_f16", 2e-6, 5e-7),
     (3, 2, (13, 11, 9), "jumps", "split_f16", 2e-5, 2e-6),
     (3, 2, (16, 12, 10), "jumps", "split_bf16", 2e-2, 2e-3),
+    (3, 3, (16, 16, 16), "smooth", "split_f16", 5e-6, 5e-6),
+    (3, 3, (13, 11, 10), "jumps", "split_f16", 2e-5, 1e-5),
+    (3, 3, (16, 12, 9), "jumps", "split_bf16", 2e-2, 2e-3),
 ]
 
 
@@ -74,21 +78,26 @@ def test_mixed_rhs_close_to_oracle(K, oracle_mod, d, R, n, kind, mode, tol_rhs, 
     assert e_rhs <= tol_rhs
 
 
-@pytest.mark.parametrize("mode", ["fp64", "split_f16"])
-def test_gate_flags_replay(K, oracle_mod, mode):
+@pytest.mark.parametrize("d,R,mode", [(2, 2, "fp64"), (2, 2, "split_f16"), (3, 3, "fp64"), (3, 3, "split_f16")])
+def test_gate_flags_replay(K, oracle_mod, d, R, mode):
     """Flags choose WENO-AO or the linear S0 value per (variable, cell); the oracle
-    replays the same decisions."""
-    say(f"case flags {mode}")
-    d, R, n = 2, 2, 48
-    U = _U("jumps", d, n, 17)
+    replays the same decisions.  Whole waves (and, in 3D, whole blocks) are linear
+    or WENO-AO, the rest mixed at random."""
+    say(f"case flags d={d} R={R} {mode}")
+    n = (48, 48) if d == 2 else (16, 16, 12)
+    ncell = int(np.prod(n))
+    U = _U("jumps", d, max(n), 17)
+    U = U[(slice(None),) + tuple(slice(0, x) for x in reversed(n))].contiguous()
     rng = np.random.default_rng(2)
-    flags = (rng.random((d + 2, n * n)) < 0.3).astype(np.uint8)
-    flags[:, : n * 4] = 0                       # whole waves linear
-    flags[:, n * 4: n * 8] = 1                  # whole waves WENO
-    orc = oracle_mod.Oracle(d, R, (n, n))
+    flags = (rng.random((d + 2, ncell)) < 0.3).astype(np.uint8)
+    plane = n[0] * n[1] if d == 3 else n[0]
+    flags[:, : 4 * plane] = 0                   # whole waves (3D: whole blocks) linear
+    flags[:, 4 * plane: 8 * plane] = 1          # whole waves WENO
+    dx = [1.0 / max(n)] * d
+    orc = oracle_mod.Oracle(d, R, n, dx=dx)
     orc.set_flags(flags)
     ref = orc.rhs(U.numpy())
-    dev = K.KFVM(d, (n, n), order=5)
+    dev = K.KFVM(d, n, dx=dx, order=2 * R + 1)
     dev.set_precision(mode)
     dev.set_checking(True)
     fl = torch.from_numpy(flags).cuda()
@@ -157,7 +166,11 @@ def test_mixed_trajectory_smooth_l1(K):
     assert l1 <= 1e-9
 
 
-def test_mixed_rejected_for_3d_r3(K):
+def test_gate_rejected_for_3d_r3(K):
+    """3D order 7 streams its operand tables; the learned gate is not fused there."""
+    from paper_2401_16543_amd import gate
     dev = K.KFVM(3, (10, 10, 10), order=7)
+    dev.set_precision("split_f16")
+    p, thr, _ = gate.load(3)
     with pytest.raises(K.KfvmError):
-        dev.set_precision("split_f16")
+        dev.set_gate(torch.from_numpy(p).cuda(), thr)
