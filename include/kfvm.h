@@ -26,8 +26,10 @@
  *  - Work is queued on the context's HIP stream (kfvm_set_stream; default the
  *    null stream) and is asynchronous unless stated otherwise.
  *  - A context owns its weight tables and workspace, allocated in kfvm_init
- *    and freed in kfvm_destroy.  Contexts are independent; one context must not
- *    be used from two threads at once.
+ *    and freed in kfvm_destroy; the per-path face buffers (float64 for the
+ *    FP64 path, float32 for the split path) are allocated on the path's first
+ *    use (out of memory then: KFVM_ERR_HIP).  Contexts are independent; one
+ *    context must not be used from two threads at once.
  */
 #ifndef KFVM_H
 #define KFVM_H

@@ -29,7 +29,7 @@ PLANS = {
     "2d_jumps_1024": dict(paths=["split_bf16", "split_f16"], gate=False),
     "3d_smooth_256": dict(paths=["split_f16", "split_f16+gate"], gate=True),
     "2d_jumps_2048": dict(paths=["split_f16+gate", "split_f16"], gate=True),
-    "3d_jumps_384_r3": dict(paths=[], gate=False),
+    "3d_jumps_384_r3": dict(paths=["split_f16"], gate=False),
 }
 
 
@@ -69,6 +69,9 @@ def run(name: str, log=print):
                 mis.append((it,) + _misclassification(dev, U, None))
             dev.step(U, dt)
         ref.step(Ur, dt)
+        if (it + 1) % max(1, steps // 10) == 0:
+            torch.cuda.synchronize()
+            print(f"# {name}: step {it + 1}/{steps} ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     out = {"workload": name, "grid": [n] * d, "R": R, "steps": steps, "seconds": round(time.time() - t0, 1),
            "status_fp64": ref.status()}

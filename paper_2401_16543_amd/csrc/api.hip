@@ -281,7 +281,6 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     int rc = KFVM_OK;
     auto A = [&](void **p, size_t bytes) { if (rc == KFVM_OK) rc = alloc(c, p, bytes); };
     A((void **)&c->d_tables, sizeof(double) * ntab);
-    A((void **)&c->work.face, sizeof(double) * (size_t)npts * nv * ncell);
     A((void **)&c->work.theta, sizeof(double) * 2 * (size_t)ncell);
     A((void **)&c->work.fbar, sizeof(double) * (size_t)dim * nv * ncell);
     A((void **)&c->work.stage[0], sizeof(double) * (size_t)nv * ncell);
@@ -328,10 +327,20 @@ static kfvm::GateArgs gate_of(kfvm_ctx *c)
     return kfvm::GateArgs{c->gate_on ? c->d_gate_w : nullptr, c->d_gate_vec, c->gate_thr, c->d_flags_out};
 }
 
+// The FP64 face buffer (n_pts * nvar float64 per cell: 122 GB at 384^3 R = 3)
+// is allocated on the first use of the FP64 reconstruction.
+static int ensure_face64(kfvm_ctx *c)
+{
+    if (c->work.face) return KFVM_OK;
+    return alloc(c, (void **)&c->work.face, sizeof(double) * (size_t)npts_of(c->dim, c->R) * c->nvar * c->geom.ncell);
+}
+
 static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
 {
     hipError_t e;
     if (c->precision == KFVM_FP64) {
+        const int rc = ensure_face64(c);
+        if (rc != KFVM_OK) return rc;
         kfvm::Tables t{c->d_tables};
         e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage, dt,
                                   c->stream, timing_of(c));
@@ -450,6 +459,8 @@ int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
     if (!U || !states) return fail(c, KFVM_ERR_ARG, "null buffer");
     hipError_t e;
     if (c->precision == KFVM_FP64) {
+        const int rc = ensure_face64(c);
+        if (rc != KFVM_OK) return rc;
         kfvm::Tables t{c->d_tables};
         e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
     } else {
@@ -541,6 +552,8 @@ int kfvm_gate_samples(kfvm_ctx *c, const double *U, float *x, float *ratio)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     if (!U || !x || !ratio) return fail(c, KFVM_ERR_ARG, "null buffer");
+    const int rc = ensure_face64(c);
+    if (rc != KFVM_OK) return rc;
     hipError_t e = kfvm::launch_gate_inputs(c->dim, c->geom, U, x, c->stream);
     kfvm::Tables t{c->d_tables};
     if (e == hipSuccess) e = kfvm::launch_recon_ratio(c->dim, c->R, c->geom, t, c->work, c->lim, U, ratio, c->stream);
