@@ -35,6 +35,7 @@ struct kfvm_ctx {
     int mix_sw = 0, mix_mode = -1;
     // learned gate (fused into the split-precision reconstruction)
     uint4 *d_gate_w = nullptr;
+    uint8_t *d_gate_raw = nullptr;   // per-cell decision bits ahead of dilation (3D order 7)
     float *d_gate_vec = nullptr;
     uint8_t *d_flags_out = nullptr;
     float gate_thr = 0.f;
@@ -324,7 +325,8 @@ static kfvm::Timing timing_of(kfvm_ctx *c) { return kfvm::Timing{c->timing, reco
 
 static kfvm::GateArgs gate_of(kfvm_ctx *c)
 {
-    return kfvm::GateArgs{c->gate_on ? c->d_gate_w : nullptr, c->d_gate_vec, c->gate_thr, c->d_flags_out};
+    return kfvm::GateArgs{c->gate_on ? c->d_gate_w : nullptr, c->d_gate_vec, c->gate_thr, c->d_flags_out,
+                          c->d_gate_raw};
 }
 
 // The FP64 face buffer (n_pts * nvar float64 per cell: 122 GB at 384^3 R = 3)
@@ -496,7 +498,7 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
         c->gate_on = 0;
         return KFVM_OK;
     }
-    if (!kfvm::gate_supported(c->dim, c->R)) return fail(c, KFVM_ERR_ARG, "the gate is not available for 3D order 7");
+    if (!kfvm::mixed_supported(c->dim, c->R)) return fail(c, KFVM_ERR_ARG, "the gate needs the split-precision path");
     const int nin = kfvm::mlp_n_in(c->dim), P = kfvm::mlp_n_params(c->dim), H = 32;
     std::vector<float> p(P);
     HIP_TRY(c, hipMemcpy(p.data(), params, sizeof(float) * P, hipMemcpyDeviceToHost));
@@ -528,6 +530,7 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
         int rc = alloc(c, (void **)&c->d_gate_w, w.size() * 2);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_gate_vec, sizeof(float) * 97);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_flags_out, (size_t)c->nvar * c->geom.ncell);
+        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_gate_raw, (size_t)c->geom.ncell);
         if (rc != KFVM_OK) return rc;
     }
     HIP_TRY(c, hipMemcpy(c->d_gate_w, w.data(), w.size() * 2, hipMemcpyHostToDevice));

@@ -67,10 +67,10 @@ struct GateArgs {
     const float *vec;
     float thr;
     uint8_t *flags_out;   // [nvar][ncell] decisions of the last evaluation (1 = WENO-AO)
+    uint8_t *raw;         // [ncell] network decisions, bit v per variable (3D order 7: before dilation)
 };
 
 bool mixed_supported(int dim, int R);
-bool gate_supported(int dim, int R);     // the learned gate runs in the split-precision kernels of (dim, R)
 int gate_operand_slots(int dim);
 int gate_slot_input(int dim, int k);   // network input fed by W1 operand column k, or -1
 int gate_w1_exp(int dim);              // power of two folded into the W1 operand

@@ -683,6 +683,96 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
 // while the previous pair is in use.  Per variable the block first agrees
 // whether any of its waves needs WENO-AO; if none does, only the S0 face-point
 // table (two tiles) passes through.
+// The learned gate on its own, for the streamed reconstruction: per cell the
+// network on the radius-2 sphere of every variable (the inputs and rules of the
+// fused gate), the decisions as bits of one byte per cell.
+template <int D, int K>
+__device__ __forceinline__ int gate_bit(const double (*tile)[MCfg<D, 2>::HN], int lc, int lane, const PhiRows<D> &ph,
+                                        const uint4 *Wg, const float *gvec, float thr, const float (&wsc)[3])
+{
+    using C = MCfg<D, 2>;
+    constexpr int KS = MixCfg<D, 2>::KS;
+    static_assert(KS == GateShape<D>::KSG, "the gate reads the radius-2 contraction slots");
+    const int hf = lane >> 5;
+    const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
+    double dl[KS][8];
+    double amax = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            dl[ks][i] = slot_increment<D, 2, K>(tile, lc, hf, 16 * ks + i, 16 * ks + 8 + i, ph, Wc);
+            amax = fmax(amax, fabs(dl[ks][i]));
+        }
+    amax = pair_max(amax);
+    int ex = 0;
+    if (amax > 0.0) frexp(amax, &ex);
+    const double sc = ldexp(1.0, SB + 1 - ex);
+    uint4 xb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        float y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = (float)(dl[ks][i] * sc);
+        xb[ks] = make_uint4(pack_bf16(y[0], y[1]), pack_bf16(y[2], y[3]), pack_bf16(y[4], y[5]), pack_bf16(y[6], y[7]));
+    }
+    const float logit = gate_forward<D>(xb, lane, Wg, gvec);
+    return logit > thr && amax > (double)wsc[K == 0 ? 0 : (K <= D ? 1 : 2)] ? 1 << K : 0;
+}
+
+template <int D, int... K>
+__device__ __forceinline__ int gate_bits(const double (*tile)[MCfg<D, 2>::HN], int lc, int lane, const PhiRows<D> &ph,
+                                         const uint4 *Wg, const float *gvec, float thr, const float (&wsc)[3],
+                                         std::integer_sequence<int, K...>)
+{
+    return (gate_bit<D, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, ph, Wg, gvec, thr,
+                           wsc) | ...);
+}
+
+template <int D>
+__global__ __launch_bounds__((MixCfg<D, 2>::NT)) void k_gate_flags(const double *__restrict__ U, Geom g, GateArgs ga)
+{
+    using C = MCfg<D, 2>;
+    using M = MixCfg<D, 2>;
+    constexpr int NV = C::NV;
+    __shared__ double tile[NV][C::HN];
+    __shared__ uint4 Wg[GateShape<D>::SLOTS];
+    __shared__ __align__(16) float gvec[100];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long tb = xcd_tile(blockIdx.x, nblk);
+    if (tb >= nblk) return;
+    const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
+    const double gam = g.gamma;
+    const Limiter off{0, 0.0};
+    load_tile<D, 2, M::NT>(U, g, off, bx * C::TX - 2, by * C::TY - 2, D == 3 ? bz * C::TZ - 2 : 0, tile,
+                           (double *)nullptr);
+    for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];
+    for (int i = threadIdx.x; i < 97; i += M::NT) gvec[i] = ga.vec[i];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;
+    const int ci = wave * 32 + (lane & 31);
+    const int tx = ci % C::TX, ty = (ci / C::TX) % C::TY, tz = ci / (C::TX * C::TY);
+    const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
+    const bool active = cx < g.n[0] && cy < g.n[1] && (D == 2 || cz < g.n[2]);
+    const long cell = active ? cx + (long)g.n[0] * (cy + (long)g.n[1] * cz) : 0;
+    const int lc = (tx + 2) + C::HX * ((ty + 2) + C::HY * (D == 3 ? tz + 2 : 0));
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
+    PhiRows<D> ph;
+    ph.init(ref, gam);
+    const double pc = pressure<D>(ref, gam);
+    const float wsc[3] = {(float)(FLAT_REL * ref[0]), (float)(FLAT_REL * sqrt(fabs(gam * pc * ph.inv_rho))),
+                          (float)(FLAT_REL * pc)};
+    int bits = gate_bits<D>(tile, lc, lane, ph, Wg, gvec, ga.thr, wsc, std::make_integer_sequence<int, NV>{});
+    if (!admissible<D>(ref, gam)) bits = (1 << NV) - 1;    // non-physical: WENO-AO (and reported by the reconstruction)
+    if (active && hf == 0) ga.raw[cell] = (uint8_t)bits;
+}
+
 template <int D, int R>
 struct StreamCfg {
     using M = MixCfg<D, R>;
@@ -722,8 +812,8 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
                                                  const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
                                                  uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
                                                  const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                                 float *__restrict__ inc, uint32_t co, long ncell, bool active,
-                                                 int sw, IncBounds &bnd)
+                                                 int gbits, uint8_t *__restrict__ fl_out, float *__restrict__ inc,
+                                                 uint32_t co, long ncell, bool active, int sw, IncBounds &bnd)
 {
     using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
@@ -764,7 +854,9 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
         bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
-    const bool use_weno = flags ? at4(flags, (long)K * ncell, co) != 0 : true;
+    // gate decisions (dilated over the 3^3 block, gbits >= 0), else the flags, else WENO-AO
+    const bool use_weno = gbits >= 0 ? ((gbits >> K) & 1) != 0 : (flags ? at4(flags, (long)K * ncell, co) != 0 : true);
+    if (gbits >= 0 && active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     const uint32_t co4 = co * 4u;
     float v2k = 0.f;
     const bool wave_weno = __any(use_weno && active);
@@ -899,28 +991,32 @@ template <int D, int R, bool BF, int... K>
 __device__ __forceinline__ void mixed_all_vars_stream(const double (*tile)[MCfg<D, R>::HN], int lc, int lane,
                                                       const uint4 *Afull, const uint4 *Alin,
                                                       uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
-                                                      const PhiRows<D> &ph, const uint8_t *flags, float *inc,
-                                                      uint32_t co, long ncell, bool active, int sw, IncBounds &bnd,
+                                                      const PhiRows<D> &ph, const uint8_t *flags, int gbits,
+                                                      uint8_t *fl_out, float *inc, uint32_t co, long ncell,
+                                                      bool active, int sw, IncBounds &bnd,
                                                       std::integer_sequence<int, K...>)
 {
     ((mixed_var_stream<D, R, K, BF>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, Afull,
-                                    Alin, buf, ph, flags, inc, co, ncell, active, sw, bnd)),
+                                    Alin, buf, ph, flags, gbits, fl_out, inc, co, ncell, active, sw, bnd)),
      ...);
 }
 
-template <int D, int R, bool BF>
+template <int D, int R, bool BF, bool GATE>
 __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     const double *__restrict__ U, const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
     float *__restrict__ inc, double *__restrict__ theta, int *__restrict__ err, const uint8_t *__restrict__ flags,
-    Geom g, Limiter lim, int sw)
+    Geom g, Limiter lim, int sw, GateArgs ga)
 {
     using C = MCfg<D, R>;
     using M = MixCfg<D, R>;
     using SC = StreamCfg<D, R>;
     constexpr int NV = C::NV;
+    // the gate's per-cell decision bits over the tile and a one-cell halo
+    constexpr int GX = C::TX + 2, GY = C::TY + 2, GZ = D == 3 ? C::TZ + 2 : 1;
     __shared__ double tile[NV][C::HN];
     __shared__ float ptile[C::HN];       // pressure of each tile cell, -1 where not admissible
     __shared__ uint4 buf[2][SC::PH * SC::TSL];
+    __shared__ uint8_t gtile[GATE ? GX * GY * GZ : 1];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
     const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
@@ -931,6 +1027,14 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     const double gam = g.gamma;
 
     load_tile<D, R, M::NT>(U, g, lim, bx * C::TX - R, by * C::TY - R, D == 3 ? bz * C::TZ - R : 0, tile, ptile);
+    if constexpr (GATE) {
+        for (int i = threadIdx.x; i < GX * GY * GZ; i += M::NT) {
+            const int hx = i % GX, hy = (i / GX) % GY, hz = i / (GX * GY);
+            const int gx = wrap_any(bx * C::TX - 1 + hx, g.n[0]), gy = wrap_any(by * C::TY - 1 + hy, g.n[1]);
+            const int gz = D == 3 ? wrap_any(bz * C::TZ - 1 + hz, g.n[2]) : 0;
+            gtile[i] = ga.raw[gx + (long)g.n[0] * (gy + (long)g.n[1] * gz)];
+        }
+    }
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;
@@ -942,6 +1046,22 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     const uint32_t co = (uint32_t)cell;
     const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
 
+    // a variable takes WENO-AO when the network marks it troubled in any cell
+    // of the 3^d block: the radius-2 inputs of the neighbours together see the
+    // radius-3 stencil
+    int gbits = -1;
+    if constexpr (GATE) {
+        const int lg = (tx + 1) + GX * ((ty + 1) + GY * (D == 3 ? tz + 1 : 0));
+        int m = 0;
+#pragma unroll
+        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) m |= gtile[lg + dx + GX * (dy + GY * dz)];
+        gbits = m;
+    }
+
     double ref[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
@@ -950,8 +1070,8 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     PhiRows<D> ph;
     ph.init(ref, gam);
     IncBounds bnd;
-    mixed_all_vars_stream<D, R, BF>(tile, lc, lane, Afull, Alin, buf, ph, flags, inc, co, g.ncell, active && ok, sw,
-                                    bnd, std::make_integer_sequence<int, NV>{});
+    mixed_all_vars_stream<D, R, BF>(tile, lc, lane, Afull, Alin, buf, ph, flags, gbits, ga.flags_out, inc, co,
+                                    g.ncell, active && ok, sw, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on)
@@ -1079,9 +1199,18 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
     const long grid = ((nblk + 7) / 8) * 8;
     mark(KT_RECON, 1);
     if constexpr (streamed_tables(D, R)) {
-        if (ga.w) return hipErrorInvalidValue;   // no gate on the streamed path
-        hipLaunchKernelGGL((k_recon_mixed_stream<D, R, BF>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin, t.full,
-                           t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw);
+        if (ga.w) {
+            using C2 = MCfg<D, 2>;
+            const long nb2 = (long)((g.n[0] + C2::TX - 1) / C2::TX) * ((g.n[1] + C2::TY - 1) / C2::TY) *
+                             ((g.n[2] + C2::TZ - 1) / C2::TZ);
+            hipLaunchKernelGGL((k_gate_flags<D>), dim3((unsigned)(((nb2 + 7) / 8) * 8)), dim3(MixCfg<D, 2>::NT), 0, s,
+                               Uin, g, ga);
+            hipLaunchKernelGGL((k_recon_mixed_stream<D, R, BF, true>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin,
+                               t.full, t.lin, w.inc32, w.theta, w.err, (const uint8_t *)nullptr, g, lim, t.sw, ga);
+        } else {
+            hipLaunchKernelGGL((k_recon_mixed_stream<D, R, BF, false>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin,
+                               t.full, t.lin, w.inc32, w.theta, w.err, w.flags_in, g, lim, t.sw, ga);
+        }
     } else {
         if (ga.w)
             hipLaunchKernelGGL((k_recon_mixed<D, R, BF, true>), dim3((unsigned)grid), dim3(M::NT), 0, s, Uin,
@@ -1109,8 +1238,6 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
 }  // namespace
 
 bool mixed_supported(int dim, int R) { return (dim == 2 || dim == 3) && (R == 2 || R == 3); }
-
-bool gate_supported(int dim, int R) { return !streamed_tables(dim, R); }
 
 int gate_operand_slots(int dim) { return dim == 2 ? GateShape<2>::SLOTS : GateShape<3>::SLOTS; }
 

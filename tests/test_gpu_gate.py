@@ -182,3 +182,46 @@ def test_gate_gain_on_exact_solution(K, case, max_weno):
     assert gated.status() == K.KFVM_OK and plain.status() == K.KFVM_OK
     assert eg <= 1.05 * ep
     assert flagged < max_weno
+
+
+def test_gate_dilated_for_3d_order7(K, oracle_mod):
+    """3D order 7: the network runs in its own kernel on the radius-2 sphere and a
+    variable takes WENO-AO where any cell of the 3^3 block is marked troubled (the
+    radius-3 stencil reaches one cell past the inputs).  Decisions against the
+    oracle network, dilated the same way (disagreements only next to logits
+    within float32 noise of the threshold); the RHS against the oracle replaying
+    the GPU's decisions."""
+    say("case gate 3D order 7")
+    d, R, n = 3, 3, (16, 16, 12)
+    U = inputs.cell_averages(inputs.discontinuous(29, d, 4, 10.0, 100.0), 16, 1.4, rule="midpoint", q=4)
+    U = U[:, :n[2], :n[1], :n[0]].contiguous()
+    dx = [1.0 / 16] * d
+    orc = oracle_mod.Oracle(d, R, n, dx=dx)
+    dev = K.KFVM(d, n, dx=dx, order=7)
+    n_in, _ = dev.mlp_sizes()
+    p = _params(n_in, 13, scale=2.0)
+    x_ref = orc.gate_inputs(U.numpy()).reshape(-1, n_in)
+    z = mlp.forward(p, x_ref, bf16=True)[0].reshape(d + 2, n[2], n[1], n[0])
+    thr = float(np.quantile(z, 0.85))
+    near = np.abs(z - thr) <= 2e-3 * (1.0 + abs(thr))
+    want = np.zeros(z.shape, dtype=bool)
+    close = np.zeros(z.shape, dtype=bool)
+    for oz in (-1, 0, 1):
+        for oy in (-1, 0, 1):
+            for ox in (-1, 0, 1):
+                want |= np.roll(z > thr, (oz, oy, ox), axis=(1, 2, 3))
+                close |= np.roll(near, (oz, oy, ox), axis=(1, 2, 3))
+    dev.set_precision("split_f16")
+    dev.set_gate(torch.from_numpy(p).cuda(), thr)
+    dev.set_checking(True)
+    L = dev.rhs(U.cuda()).cpu().numpy()
+    flags = dev.get_flags().cpu().numpy().reshape(z.shape)
+    bad = flags.astype(bool) != want
+    say(f"  WENO-AO on {flags.mean():.3f}  disagreements {int(bad.sum())} (all next to near-threshold logits: "
+        f"{bool(np.all(close[bad]))})")
+    assert np.all(close[bad]) and bad.mean() <= 0.02
+    orc.set_flags(flags.reshape(d + 2, -1))
+    ref = orc.rhs(U.numpy())
+    e = max(np.abs(L[k] - ref[k]).max() / np.abs(ref[k]).max() for k in range(d + 2))
+    say(f"  gated rhs rel err {e:.2e}")
+    assert e <= 2e-5

@@ -164,13 +164,3 @@ def test_mixed_trajectory_smooth_l1(K):
     l1 = float((Ua[0] - Ub[0]).abs().mean())
     say(f"  L1 rho diff {l1:.3e}")
     assert l1 <= 1e-9
-
-
-def test_gate_rejected_for_3d_r3(K):
-    """3D order 7 streams its operand tables; the learned gate is not fused there."""
-    from paper_2401_16543_amd import gate
-    dev = K.KFVM(3, (10, 10, 10), order=7)
-    dev.set_precision("split_f16")
-    p, thr, _ = gate.load(3)
-    with pytest.raises(K.KfvmError):
-        dev.set_gate(torch.from_numpy(p).cuda(), thr)
