@@ -71,6 +71,8 @@ def _load():
         _lib.oracle_omega_ratio.argtypes = [P(_Ctx), P(C.c_double), P(C.c_float)]
         _lib.oracle_omega_ratio.restype = C.c_int
         _lib.oracle_phi.argtypes = [P(_Ctx), P(C.c_double), P(C.c_double), P(C.c_double)]
+        _lib.oracle_smoothness.argtypes = [P(_Ctx), P(C.c_double), C.c_long, P(C.c_double)]
+        _lib.oracle_smoothness.restype = C.c_int
         _lib.oracle_phi.restype = None
     return _lib
 
@@ -201,6 +203,13 @@ class Oracle:
         B = np.empty((self.nvar, self.nvar))
         self._lib.oracle_phi(C.byref(self._ctx), _ptr(ref), _ptr(A), _ptr(B))
         return A, B
+
+    def smoothness(self, U, cell: int):
+        """Smoothness indicators beta[variable, stencil] of one cell (eq. smoothIndic)."""
+        U = self._check_U(U)
+        out = np.empty((self.nvar, self._ctx.nst))
+        self._call(self._lib.oracle_smoothness(C.byref(self._ctx), _ptr(U), int(cell), _ptr(out)))
+        return out
 
     def omega_ratio(self, U):
         """omega_0 / gamma_0 of the WENO-AO weights per (variable, cell): [nvar, cells] float32."""

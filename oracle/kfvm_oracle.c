@@ -146,15 +146,18 @@ static void matvec(int nv, const double *A, const double *x, double *y)
 
 /* --------------------------------------------- Riemann states of one cell --- */
 /* states: [n_pts][nvar].  Returns OK or ERR_NONPHYSICAL. */
-static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio);
+static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio,
+                          double *betas);
 
 static int cell_states(const oracle_ctx *c, const double *U, long cell, double *states)
 {
-    return cell_states_ex(c, U, cell, states, NULL);
+    return cell_states_ex(c, U, cell, states, NULL, NULL);
 }
 
-/* ratio (optional): omega_0 / gamma_0 per variable, 1 where the variable is linear */
-static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio)
+/* ratio (optional): omega_0 / gamma_0 per variable, 1 where the variable is linear;
+ * betas (optional): the smoothness indicator of every stencil, betas[k * nst + q] */
+static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, double *states, float *ratio,
+                          double *betas)
 {
     int nv = c->nvar, n0 = c->n0, np = c->n_pts, nd = c->n_der;
     long N = ncells(c);
@@ -193,6 +196,7 @@ static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, doubl
                 b += acc * acc;
             }
             beta[q] = b;
+            if (betas) betas[k * c->nst + q] = b;
         }
         int use_weno = c->weno;
         if (c->flags) use_weno = c->flags[(long)k * N + cell] != 0;
@@ -501,7 +505,7 @@ int oracle_omega_ratio(const oracle_ctx *c, const double *U, float *out)
     for (long cell = 0; cell < N; ++cell) {
         double *st = (double *)malloc(sizeof(double) * c->n_pts * nv);
         float r[MAXV];
-        int e = cell_states_ex(c, U, cell, st, r);
+        int e = cell_states_ex(c, U, cell, st, r, NULL);
         if (e != OK) {
 #pragma omp atomic write
             err = e;
@@ -510,6 +514,15 @@ int oracle_omega_ratio(const oracle_ctx *c, const double *U, float *out)
         free(st);
     }
     return err;
+}
+
+/* Smoothness indicators beta[k][q] (eq. smoothIndic) of one cell, for unit tests. */
+int oracle_smoothness(const oracle_ctx *c, const double *U, long cell, double *beta)
+{
+    double *st = (double *)malloc(sizeof(double) * c->n_pts * c->nvar);
+    int e = cell_states_ex(c, U, cell, st, NULL, beta);
+    free(st);
+    return e;
 }
 
 /* Phi and Phi^-1 at a reference state, for unit tests. */

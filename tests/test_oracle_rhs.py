@@ -344,3 +344,47 @@ def test_phi_is_jacobian_and_inverse(oracle_mod, d):
             e[j] = h
             J[:, j] = (V(U + e) - V(U - e)) / (2 * h)
         assert np.allclose(A, J, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("d,R", [(2, 2), (2, 3), (3, 2)])
+def test_smoothness_indicator_closed_form(oracle_mod, d, R):
+    """eq. smoothIndic pinned by polynomials: on cell averages of a polynomial that
+    a stencil reproduces (degree <= p_q), beta_q equals the sum over
+    0 < |alpha| <= R of (d^alpha f(0))^2 in unit-cell coordinates, f being the
+    reconstruction variable W_K = Phi_K(U_c) U.  Linear data for every stencil,
+    quadratic data for the stencils with p_q >= 2."""
+    from oracle import weights as W
+    T = W.tables(d, R)
+    n, nv = 12, d + 2
+    rng = np.random.default_rng(3)
+    base = np.array([1.0] + [0.3] * d + [3.0])
+    g = 0.02 * rng.standard_normal((nv, d))                 # gradient of each conserved field
+    h = 0.01 * rng.standard_normal((nv, d, d))
+    h = 0.5 * (h + np.transpose(h, (0, 2, 1)))               # symmetric quadratic part
+    centre = (n // 2,) * d
+    orc = oracle_mod.Oracle(d, R, (n,) * d)
+    cell = sum(centre[a] * n ** a for a in range(d))
+    for quadratic in (False, True):
+        U = np.empty((nv,) + (n,) * d)
+        for idx in np.ndindex(*((n,) * d)):
+            o = np.array([idx[d - 1 - a] - centre[a] for a in range(d)], dtype=float)   # (x, y[, z]) offsets
+            val = base.copy()
+            if np.all(np.abs(o) <= R):
+                val = val + g @ o
+                if quadratic:
+                    # cell average of x_a x_b over the unit cell at offset o
+                    avg = np.outer(o, o) + np.eye(d) / 12.0
+                    val = val + np.einsum("jab,ab->j", h, avg)
+            U[(slice(None),) + idx] = val
+        beta = orc.smoothness(U, cell)
+        Phi, _ = orc.phi(U.reshape(nv, -1)[:, cell])
+        for k in range(nv):
+            want = float(np.sum((Phi[k] @ g) ** 2))
+            if quadratic:
+                for a in range(d):
+                    for b in range(a, d):
+                        want += float((2.0 * Phi[k] @ h[:, a, b]) ** 2)
+            for q, p in enumerate(T["degrees"]):
+                if quadratic and p < 2:
+                    continue
+                assert beta[k, q] == pytest.approx(want, rel=1e-7), (quadratic, k, q, p)
