@@ -164,3 +164,46 @@ def test_mixed_trajectory_smooth_l1(K):
     l1 = float((Ua[0] - Ub[0]).abs().mean())
     say(f"  L1 rho diff {l1:.3e}")
     assert l1 <= 1e-9
+
+
+@pytest.mark.parametrize("d,R,n", [(2, 3, (32, 32)), (3, 2, (16, 16, 16)), (3, 3, (16, 16, 12))])
+def test_mixed_limiter_engaged(K, oracle_mod, d, R, n):
+    """Strong jumps (density ratios to 100, pressure ratios to 1000) and kappa =
+    0.1 so the positivity limiter acts: the split path's running-bound limiter
+    (exact per-point fallback) against the oracle's per-point limiter."""
+    say(f"case mixed limiter d={d} R={R} n={n}")
+    gamma = 1.4
+    U = inputs.cell_averages(inputs.discontinuous(9, d, 6 if d == 2 else 4, 100.0, 1000.0), max(n), gamma,
+                             rule="midpoint", q=4 if d == 2 else 2)
+    U = U[(slice(None),) + tuple(slice(0, x) for x in reversed(n))].contiguous()
+    dx = [1.0 / max(n)] * d
+    orc = oracle_mod.Oracle(d, R, n, dx=dx, gamma=gamma, kappa=0.1)
+    free = oracle_mod.Oracle(d, R, n, dx=dx, gamma=gamma, limiter=False).states(U.numpy())
+    ref_states = orc.states(U.numpy())
+    assert np.abs(free - ref_states).max() > 1e-6          # the limiter acted
+    dev = K.KFVM(d, n, dx=dx, order=2 * R + 1, gamma=gamma)
+    dev.set_precision("split_f16")
+    dev.set_limiter(True, 0.1)
+    dev.set_checking(True)
+    Ud = U.cuda()
+    st = dev.face_states(Ud).cpu().numpy()
+    e_st = rel_err(np.moveaxis(st, -1, 0), np.moveaxis(ref_states, -1, 0))
+    e_rhs = rel_err(dev.rhs(Ud).cpu().numpy(), orc.rhs(U.numpy()))
+    say(f"  states rel err {e_st:.3e}  rhs rel err {e_rhs:.3e}")
+    assert e_st <= 2e-5 and e_rhs <= 2e-5
+
+
+def test_mixed_hll(K, oracle_mod):
+    """The HLL option in the split path (the Riemann solver itself is float64)."""
+    say("case mixed hll")
+    d, R, n = 2, 2, (40, 36)
+    U = _U("jumps", d, 40, 23)[:, :n[1], :n[0]].contiguous()
+    dx = [1.0 / 40] * d
+    orc = oracle_mod.Oracle(d, R, n, dx=dx, riemann="hll")
+    dev = K.KFVM(d, n, dx=dx, order=5)
+    dev.set_precision("split_f16")
+    dev.set_riemann("hll")
+    dev.set_checking(True)
+    e = rel_err(dev.rhs(U.cuda()).cpu().numpy(), orc.rhs(U.numpy()))
+    say(f"  rhs rel err {e:.3e}")
+    assert e <= 2e-5
