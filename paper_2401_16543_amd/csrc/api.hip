@@ -21,6 +21,7 @@ struct kfvm_ctx {
     int checking = 0;
     hipStream_t stream = nullptr;
     double *d_tables = nullptr;
+    double *d_wch = nullptr;          // chunk-major copy of the tables (3D R = 3 FP64 path)
     kfvm::Work work{};
     double *d_dt = nullptr;
     std::vector<void *> allocs;
@@ -297,6 +298,29 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     }
     c->host_tables = host;
     hipError_t e = hipMemcpy(c->d_tables, host.data(), sizeof(double) * ntab, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dim == 3 && R == 3) {
+        // chunk-major copy for the chunked FP64 reconstruction: per chunk a [row][CH]
+        // block of its stencil's weights, zeros in the padding
+        using L = kfvm::ChunkLayout<3, 3, kfvm::FP64_CHUNK>;
+        using S = kfvm::Stencil<3, 3>;
+        static constexpr L lay{};
+        static constexpr S st{};
+        std::vector<double> wch((size_t)L::NCH * S::NROWS * L::CH, 0.0);
+        for (int q = 0; q < S::NST; ++q)
+            for (int k = lay.cb[q]; k < lay.cb[q + 1]; ++k)
+                for (int row = 0; row < S::NROWS; ++row)
+                    for (int j = 0; j < L::CH; ++j) {
+                        const int m = (k - lay.cb[q]) * L::CH + j;
+                        if (m < st.nmem[q])
+                            wch[((size_t)k * S::NROWS + row) * L::CH + j] = host[st.tab[q] + row * st.nmem[q] + m];
+                    }
+        if (alloc(c, (void **)&c->d_wch, sizeof(double) * wch.size()) != KFVM_OK) {
+            g_init_msg = c->msg;
+            kfvm_destroy(c);
+            return KFVM_ERR_HIP;
+        }
+        e = hipMemcpy(c->d_wch, wch.data(), sizeof(double) * wch.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemset(c->work.err, 0, sizeof(int) * 4);
     if (e != hipSuccess) {
         hip_fail(nullptr, e, "upload");
@@ -343,7 +367,7 @@ static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *
     if (c->precision == KFVM_FP64) {
         const int rc = ensure_face64(c);
         if (rc != KFVM_OK) return rc;
-        kfvm::Tables t{c->d_tables};
+        kfvm::Tables t{c->d_tables, c->d_wch};
         e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage, dt,
                                   c->stream, timing_of(c));
     } else {
@@ -463,7 +487,7 @@ int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
     if (c->precision == KFVM_FP64) {
         const int rc = ensure_face64(c);
         if (rc != KFVM_OK) return rc;
-        kfvm::Tables t{c->d_tables};
+        kfvm::Tables t{c->d_tables, c->d_wch};
         e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
     } else {
         kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
@@ -558,7 +582,7 @@ int kfvm_gate_samples(kfvm_ctx *c, const double *U, float *x, float *ratio)
     const int rc = ensure_face64(c);
     if (rc != KFVM_OK) return rc;
     hipError_t e = kfvm::launch_gate_inputs(c->dim, c->geom, U, x, c->stream);
-    kfvm::Tables t{c->d_tables};
+    kfvm::Tables t{c->d_tables, c->d_wch};
     if (e == hipSuccess) e = kfvm::launch_recon_ratio(c->dim, c->R, c->geom, t, c->work, c->lim, U, ratio, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return c->checking ? sync_check(c) : KFVM_OK;

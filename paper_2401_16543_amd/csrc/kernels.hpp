@@ -40,8 +40,11 @@ struct MixTables {
 };
 
 struct Tables {
-    const double *w;   // packed reconstruction tables (device)
+    const double *w;      // packed reconstruction tables (device)
+    const double *wch;    // the same in chunk layout (ChunkLayout<3, 3, 8>), 3D R = 3 only
 };
+
+constexpr int FP64_CHUNK = 8;    // members per chunk of the chunked FP64 reconstruction
 
 // Optional per-kernel timing: when `on`, every launch is bracketed by HIP events
 // on the launch stream; the host sums the elapsed times later.

@@ -125,23 +125,158 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
         }
     }
     if constexpr (K >= 1 && K <= D) fb.v2 += v2k;
+    // settle the bounds here: sunk to their use they would keep every face value
+    // of the variable live through the later passes
+    asm volatile("" : "+v"(fb.rlo), "+v"(fb.rhi), "+v"(fb.plo), "+v"(fb.v2));
+}
+
+// 3D R = 3 holds too many S0 values per variable for the register-blocked form
+constexpr bool chunked_fp64(int dim, int R) { return dim == 3 && R == 3; }
+
+// LDS offsets (in the FP64 tile) of the chunked member slots; padding reads the centre
+template <int D, int R>
+struct ChunkOffsets {
+    using L = ChunkLayout<D, R, FP64_CHUNK>;
+    int off[L::NCH * L::CH];
+    constexpr ChunkOffsets() : off{}
+    {
+        using C = Cfg<D, R>;
+        constexpr L lay{};
+        constexpr typename C::S st{};
+        for (int i = 0; i < L::NCH * L::CH; ++i) {
+            const int h = lay.member[i];
+            off[i] = h < 0 ? 0 : st.off[h][0] + C::HX * (st.off[h][1] + C::HY * st.off[h][2]);
+        }
+    }
+};
+
+// Reconstruction of variable K for stencils too large to hold in VGPRs (3D
+// R = 3: 123 S0 values per variable).  The members of every stencil are walked
+// in chunks of FP64_CHUNK: the first pass accumulates each stencil's derivative
+// rows and its smoothness indicator (eq. smoothIndic, members in the oracle's
+// order), the second the WENO-AO blend (eq. wenoAOrec) of the point rows
+// directly, each chunk's values scaled by its stencil's coefficient.  Weights
+// come through scalar loads, one [row][chunk] block of the chunk-major table per
+// chunk; stencil indices run in rolled loops, the per-stencil values move
+// through small shift registers.
+template <int D, int R, int K>
+__device__ __forceinline__ void recon_var_chunked(const double (*tile)[Cfg<D, R>::HN], int lc,
+                                                  const double *__restrict__ wch, const PhiRows<D> &ph,
+                                                  const uint8_t *__restrict__ flags, double *__restrict__ face,
+                                                  long cell, long ncell, float *__restrict__ ratio, FaceBounds &fb)
+{
+    using C = Cfg<D, R>;
+    using S = typename C::S;
+    using L = ChunkLayout<D, R, FP64_CHUNK>;
+    constexpr int NV = C::NV, NST = S::NST, NPTS = S::NPTS, NDER = S::NDER, NROWS = S::NROWS, CH = L::CH;
+    static constexpr L lay{};
+    static constexpr ChunkOffsets<D, R> co{};
+    const bool use_weno = flags ? flags[(long)K * ncell + cell] != 0 : true;
+    double cq[NST];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) cq[q] = q == 0 ? 1.0 : 0.0;
+    if (use_weno) {
+        double beta[NST];
+#pragma unroll 1
+        for (int q = 0; q < NST; ++q) {
+            double acc[NDER];
+#pragma unroll
+            for (int a = 0; a < NDER; ++a) acc[a] = 0.0;
+#pragma unroll 1
+            for (int k = lay.cb[q]; k < lay.cb[q + 1]; ++k) {
+                double gv[CH];
+#pragma unroll
+                for (int j = 0; j < CH; ++j) gv[j] = w_component<D, K, C::HN>(tile, lc + co.off[k * CH + j], ph);
+                const double *blk = wch + (long)k * NROWS * CH + NPTS * CH;
+#pragma unroll
+                for (int a = 0; a < NDER; ++a)
+#pragma unroll
+                    for (int j = 0; j < CH; ++j) acc[a] += blk[a * CH + j] * gv[j];
+            }
+            double b = 0.0;
+#pragma unroll
+            for (int a = 0; a < NDER; ++a) b += acc[a] * acc[a];
+#pragma unroll
+            for (int i = 0; i + 1 < NST; ++i) beta[i] = beta[i + 1];
+            beta[NST - 1] = b;
+        }
+        double om[NST], sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            om[q] = lin_w<D>(q) * rcp64(beta[q] * beta[q] + EPS_WENO);
+            sum += om[q];
+        }
+        const double isum = rcp64(sum);
+#pragma unroll
+        for (int q = 0; q < NST; ++q) om[q] *= isum;
+        cq[0] = om[0] * inv_lin0<D>();
+#pragma unroll
+        for (int q = 1; q < NST; ++q) cq[q] = om[q] - om[0] * lin_ratio<D>(q);
+    }
+    if (ratio) ratio[(long)K * ncell + cell] = (float)cq[0];   // omega_0 / gamma_0 (1 when linear)
+    const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
+    double f[NPTS];
+#pragma unroll
+    for (int s = 0; s < NPTS; ++s) f[s] = 0.0;
+    const int qend = use_weno ? NST : 1;
+#pragma unroll 1
+    for (int q = 0; q < qend; ++q) {
+        const double c = cq[0];
+#pragma unroll
+        for (int i = 0; i + 1 < NST; ++i) cq[i] = cq[i + 1];
+#pragma unroll 1
+        for (int k = lay.cb[q]; k < lay.cb[q + 1]; ++k) {
+            double gv[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) gv[j] = c * w_component<D, K, C::HN>(tile, lc + co.off[k * CH + j], ph);
+            const double *blk = wch + (long)k * NROWS * CH;
+#pragma unroll
+            for (int s = 0; s < NPTS; ++s)
+#pragma unroll
+                for (int j = 0; j < CH; ++j) f[s] += blk[s * CH + j] * gv[j];
+        }
+    }
+    double v2k = 0.0;
+#pragma unroll
+    for (int s = 0; s < NPTS; ++s) {
+        face[(s * NV + K) * ncell + cell] = f[s];
+        if constexpr (K == 0) {
+            fb.rlo = fmin(fb.rlo, f[s]);
+            fb.rhi = fmax(fb.rhi, f[s]);
+        } else if constexpr (K == D + 1) {
+            fb.plo = fmin(fb.plo, f[s] - Wc);
+        } else {
+            v2k = fmax(v2k, (f[s] - Wc) * (f[s] - Wc));
+        }
+    }
+    if constexpr (K >= 1 && K <= D) fb.v2 += v2k;
+    // settle the bounds here: sunk to their use they would keep every face value
+    // of the variable live through the later passes
+    asm volatile("" : "+v"(fb.rlo), "+v"(fb.rhi), "+v"(fb.plo), "+v"(fb.v2));
 }
 
 template <int D, int R, int... K>
 __device__ __forceinline__ void recon_all_vars(const double (*tile)[Cfg<D, R>::HN], int lc, const double *__restrict__ wt,
-                                               const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
-                                               double *__restrict__ face, long cell, long ncell, float *ratio,
-                                               FaceBounds &fb, std::integer_sequence<int, K...>)
+                                               const double *__restrict__ wch, const PhiRows<D> &ph,
+                                               const uint8_t *__restrict__ flags, double *__restrict__ face, long cell,
+                                               long ncell, float *ratio, FaceBounds &fb,
+                                               std::integer_sequence<int, K...>)
 {
     // one pass per variable; the empty asm keeps each pass's LDS reads from
     // being hoisted into a single register-hungry prologue
-    ((recon_var<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wt, ph, flags, face,
-                         cell, ncell, ratio, fb)),
-     ...);
+    if constexpr (chunked_fp64(D, R))
+        ((recon_var_chunked<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wch, ph,
+                                     flags, face, cell, ncell, ratio, fb)),
+         ...);
+    else
+        ((recon_var<D, R, K>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), wt, ph, flags, face,
+                             cell, ncell, ratio, fb)),
+         ...);
 }
 
 template <int D, int R>
 __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restrict__ U, const double *__restrict__ wt,
+                                                         const double *__restrict__ wch,
                                                          double *__restrict__ face, double *__restrict__ theta,
                                                          int *__restrict__ err, const uint8_t *__restrict__ flags,
                                                          Geom g, Limiter lim, float *__restrict__ ratio)
@@ -198,7 +333,7 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     PhiRows<D> ph;
     ph.init(ref, gam);
     FaceBounds fb;
-    recon_all_vars<D, R>(tile, lc, wt, ph, flags, face, cell, g.ncell, ratio, fb,
+    recon_all_vars<D, R>(tile, lc, wt, wch, ph, flags, face, cell, g.ncell, ratio, fb,
                          std::make_integer_sequence<int, NV>{});
 
     // positivity limiter (section 4) on the cell's Riemann states
@@ -457,7 +592,7 @@ hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;   // every XCD gets the same number of slots
     mark(KT_RECON, 1);
-    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, Uin, t.w, w.face, w.theta, w.err,
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, Uin, t.w, t.wch, w.face, w.theta, w.err,
                        w.flags_in, g, lim, (float *)nullptr);
     mark(KT_RECON, 0);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
@@ -478,7 +613,7 @@ hipError_t states_impl(const Geom &g, const Tables &t, const Work &w, const Limi
     const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, w.face, w.theta, w.err,
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, t.wch, w.face, w.theta, w.err,
                        w.flags_in, g, lim, (float *)nullptr);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     hipLaunchKernelGGL((k_states<D, R>), dim3(nb), dim3(256), 0, s, U, w.face, w.theta, states, g);
@@ -506,7 +641,7 @@ hipError_t ratio_impl(const Geom &g, const Tables &t, const Work &w, const Limit
     const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     const long grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, w.face, w.theta, w.err,
+    hipLaunchKernelGGL((k_recon<D, R>), dim3((unsigned)grid), dim3(C::NT), 0, s, U, t.w, t.wch, w.face, w.theta, w.err,
                        (const uint8_t *)nullptr, g, lim, ratio);
     return hipGetLastError();
 }

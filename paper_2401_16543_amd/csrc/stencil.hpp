@@ -135,6 +135,39 @@ static_assert(centre_is_middle<2, 2>() && centre_is_middle<2, 3>() && centre_is_
                   centre_is_middle<3, 3>(),
               "S0 centre must sit in the middle of the lexicographic order");
 
+// Members of every stencil in chunks of CH (the FP64 reconstruction of large
+// stencils walks them chunk by chunk): stencil q's members padded with -1 to a
+// multiple of CH; chunk k covers member slots [CH k, CH k + CH) and belongs to
+// stencil q for cb[q] <= k < cb[q + 1].  The padded weights are laid out per
+// chunk as [row][CH] (rows: face points, then derivatives), zeros in padding.
+template <int D, int R, int CH_>
+struct ChunkLayout {
+    using S = Stencil<D, R>;
+    static constexpr int CH = CH_;
+    static constexpr int total_chunks()
+    {
+        constexpr S st{};
+        int n = 0;
+        for (int q = 0; q < S::NST; ++q) n += (st.nmem[q] + CH - 1) / CH;
+        return n;
+    }
+    static constexpr int NCH = total_chunks();
+    int cb[S::NST + 1];       // first chunk of each stencil
+    int member[NCH * CH];     // S0 index of each padded member slot, -1 for padding
+    constexpr ChunkLayout() : cb{}, member{}
+    {
+        constexpr S st{};
+        int k = 0;
+        for (int q = 0; q < S::NST; ++q) {
+            cb[q] = k;
+            const int nc = (st.nmem[q] + CH - 1) / CH;
+            for (int m = 0; m < nc * CH; ++m) member[k * CH + m] = m < st.nmem[q] ? st.mem[q][m] : -1;
+            k += nc;
+        }
+        cb[S::NST] = k;
+    }
+};
+
 // linear weights of section 3.2 (gamma_hi = gamma_lo = 0.8)
 template <int D>
 constexpr double linear_weight(int q)
