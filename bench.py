@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d_smooth_256")
     ap.add_argument("--mixed", default="split_f16", help="split_f16 or split_bf16")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) to scale HBM counters")
