@@ -279,7 +279,7 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
         }
     }
 
-    const int nv = c->nvar, npts = npts_of(dim, R);
+    const int nv = c->nvar;
     int rc = KFVM_OK;
     auto A = [&](void **p, size_t bytes) { if (rc == KFVM_OK) rc = alloc(c, p, bytes); };
     A((void **)&c->d_tables, sizeof(double) * ntab);
@@ -336,7 +336,10 @@ static void record_event(void *self, int kind, hipStream_t s, int begin)
     kfvm_ctx *c = (kfvm_ctx *)self;
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return;
-    hipEventRecord(ev, s);
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return;
+    }
     if (begin) {
         c->pending[kind] = ev;
     } else {
@@ -598,7 +601,7 @@ int kfvm_mlp_train_step(kfvm_ctx *c, const float *x, const float *y, int B, floa
     if (need > c->mlp_ws_floats) {
         if (c->d_mlp_ws) {
             HIP_TRY(c, hipStreamSynchronize(c->stream));
-            hipFree(c->d_mlp_ws);
+            HIP_TRY(c, hipFree(c->d_mlp_ws));
             for (auto &p : c->allocs)
                 if (p == c->d_mlp_ws) p = nullptr;
         }
@@ -631,8 +634,8 @@ int kfvm_kernel_times(kfvm_ctx *c, double *ms, long long *launches, int n)
             ms[e.first] += t;
             launches[e.first] += 1;
         }
-        hipEventDestroy(e.second.first);
-        hipEventDestroy(e.second.second);
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
     }
     c->events.clear();
     return KFVM_OK;
@@ -646,10 +649,13 @@ const char *kfvm_last_error(const kfvm_ctx *c)
 void kfvm_destroy(kfvm_ctx *c)
 {
     if (!c) return;
-    hipStreamSynchronize(c->stream);
-    for (auto &e : c->events) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->events) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
     for (void *p : c->allocs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete c;
 }
 

@@ -283,7 +283,7 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
 {
     using C = Cfg<D, R>;
     using S = typename C::S;
-    constexpr int NV = C::NV, N0 = S::N0, NST = S::NST, NPTS = S::NPTS, NDER = S::NDER;
+    constexpr int NV = C::NV, NPTS = S::NPTS;
     __shared__ double tile[NV][C::HN];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
