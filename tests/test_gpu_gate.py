@@ -107,13 +107,13 @@ def test_gate_samples_match_oracle(K, oracle_mod, d, n):
     assert er <= 1e-5
 
 
-@pytest.mark.parametrize("d,n", [(2, 48), (3, 16)])
-def test_fused_gate_decisions_and_replay(K, oracle_mod, d, n):
-    say(f"case fused gate d={d}")
+@pytest.mark.parametrize("d,R,n", [(2, 2, 48), (2, 3, 48), (3, 2, 16)])
+def test_fused_gate_decisions_and_replay(K, oracle_mod, d, R, n):
+    say(f"case fused gate d={d} R={R}")
     U = inputs.cell_averages(inputs.discontinuous(23, d, 6 if d == 2 else 4, 10.0, 100.0), n, 1.4,
                              rule="midpoint", q=4)
-    orc = oracle_mod.Oracle(d, 2, (n,) * d)
-    dev = K.KFVM(d, (n,) * d, order=5)
+    orc = oracle_mod.Oracle(d, R, (n,) * d)
+    dev = K.KFVM(d, (n,) * d, order=2 * R + 1)
     n_in, _ = dev.mlp_sizes()
     p = _params(n_in, 9, scale=2.0)
     x_ref = orc.gate_inputs(U.numpy()).reshape(-1, n_in)
