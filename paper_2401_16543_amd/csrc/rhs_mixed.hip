@@ -3,18 +3,20 @@
 // The weight-apply and smoothness-indicator contractions run on
 // v_mfma_f32_32x32x16_{f16,bf16}: each operand x is split into hi = half(x) and
 // lo = half(x - hi), and A.B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi is accumulated
-// in float32.  Everything around them stays in float64: the increments fed to
-// the matrix cores, the smoothness-indicator squares, the nonlinear weights and
-// their normalisation (eps = 1e-40 is far below the float32 range), the WENO-AO
-// blend, the positivity limiter, the Riemann solver and the Runge-Kutta update.
+// in float32.  The increments fed to the matrix cores are formed in float64;
+// the smoothness-indicator sums of squares and the blend sums take the float32
+// accumulator values; the nonlinear weights and their normalisation are float64
+// (eps = 1e-40 is far below the float32 range), and so are the positivity
+// limiter, the Riemann solver and the Runge-Kutta update.
 //
 // Contraction layout (one wave = 32 cells, both half-waves on the same cells):
 //   B (K x N): the increments delta_h = W_h - W_c of one reconstruction variable
-//      over S0 (K, padded to 16), for the wave's 32 cells (N).  Because the point
-//      rows of every table sum to one and the derivative rows to zero, point
-//      values are W_c + R.delta and derivatives R.delta exactly; the increments
-//      are small on smooth data, so the split keeps ~22 significant bits of
-//      them.  They are scaled per cell by a power of two to [2^13, 2^14).
+//      over S0 less its centre (whose increment is zero; K padded to 16), for
+//      the wave's 32 cells (N).  Because the point rows of every table sum to
+//      one and the derivative rows to zero, point values are W_c + R.delta and
+//      derivatives R.delta exactly; the increments are small on smooth data, so
+//      the split keeps ~22 significant bits of them.  They are scaled per cell
+//      by a power of two to [2^13, 2^14).
 //   A (M x K): every stencil's table embedded in S0 columns (zeros outside the
 //      stencil), rows interleaved as target * 8 + stencil, weights scaled by 2^SW.
 //      In the 32 x 32 accumulator layout a lane then holds, for each of four
@@ -23,10 +25,12 @@
 //      lane-local partial sums plus one exchange between the half-waves.
 //   A second table holds only the S0 face-point rows (targets as rows): a wave
 //   whose 32 cells the gate marks as smooth for a variable uses it alone.
+// The tables sit in LDS; for 3D R = 3 they are too large and stream through an
+// LDS window (k_recon_mixed_stream).
 // The kernel writes the blended increments w_s - W_c as float32 (half the bytes
 // of the float64 path; the value is a float32 matrix-core sum to begin with),
-// and the limiter's two factors; the face-flux kernel rebuilds
-// u_s = U_c + theta Phi^-1 (w_s - W_c).
+// and the limiter's two factors, found from running bounds of the stored
+// increments; the face-flux kernel rebuilds u_s = U_c + theta Phi^-1 (w_s - W_c).
 #include "device_common.hpp"
 
 namespace kfvm {
