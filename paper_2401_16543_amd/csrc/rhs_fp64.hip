@@ -10,8 +10,11 @@
 //           smoothness indicators and WENO-JS weights in FP64 (section 3.3), then
 //           the point rows blended by WENO-AO (eq. wenoAOrec).  The blended
 //           values go to the face buffer in reconstruction variables; the
-//           positivity limiter of section 4 then reads them back (L2-resident)
-//           and stores the cell's two scaling factors.
+//           positivity limiter of section 4 takes its factors from running
+//           bounds of those values (re-reading them only for a cell whose
+//           pressure bound fails) and stores the cell's two scaling factors.
+//           3D R = 3 walks each stencil's members in chunks instead of holding
+//           all 123 S0 values (recon_var_chunked).
 //   flux    one thread per cell, Riemann problem at the Gauss points of each
 //           of its lower faces (states rebuilt as U~ + theta (Phi^-1 w - U~)),
 //           HLLC or HLL with Batten wavespeeds, Gauss sum; one flux per face.
