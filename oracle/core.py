@@ -44,7 +44,7 @@ class _Ctx(C.Structure):
         ("lin_w", C.POINTER(C.c_double)), ("n_pts", C.c_int), ("n_der", C.c_int),
         ("gl_w", C.POINTER(C.c_double)), ("eps", C.c_double),
         ("limiter", C.c_int), ("kappa", C.c_double), ("riemann", C.c_int),
-        ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)),
+        ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)), ("kxrcf_m", C.c_double),
     ]
 
 
@@ -74,6 +74,11 @@ def _load():
         _lib.oracle_smoothness.argtypes = [P(_Ctx), P(C.c_double), C.c_long, P(C.c_double)]
         _lib.oracle_smoothness.restype = C.c_int
         _lib.oracle_phi.restype = None
+        _lib.oracle_kxrcf.argtypes = [P(_Ctx), P(C.c_double), C.c_double, P(C.c_uint8), P(C.c_double),
+                                      P(C.c_double)]
+        _lib.oracle_kxrcf.restype = C.c_int
+        _lib.oracle_kxrcf_cells.argtypes = [P(_Ctx), P(C.c_double), C.c_long, P(C.c_long), P(C.c_double)]
+        _lib.oracle_kxrcf_cells.restype = C.c_int
     return _lib
 
 
@@ -89,7 +94,8 @@ class Oracle:
     """Plain CPU KFVM-WENO on a periodic box of n cells per axis."""
 
     def __init__(self, d: int, R: int, n, dx=None, gamma: float = 1.4, *, limiter: bool = True,
-                 kappa: float = 0.5, riemann: str = "hllc", weno: bool = True, tables=None):
+                 kappa: float = 0.5, riemann: str = "hllc", weno: bool = True, tables=None,
+                 kxrcf_m: float | None = None):
         self.d, self.R = d, R
         self.nvar = d + 2
         n = list(n) + [1] * (3 - len(n))
@@ -132,6 +138,7 @@ class Oracle:
         ctx.riemann = {"hllc": 0, "hll": 1}[riemann]
         ctx.weno = int(weno)
         ctx.flags = C.POINTER(C.c_uint8)()
+        ctx.kxrcf_m = float(kxrcf_m) if kxrcf_m else 0.0
         self._ctx = ctx
         self._lib = _load()
 
@@ -145,6 +152,36 @@ class Oracle:
     def _call(self, rc):
         if rc != 0:
             raise OracleError(f"oracle returned {rc}")
+
+    def set_kxrcf(self, m):
+        """The KXRCF indicator (section 3.5) with threshold Delta^m picks the WENO
+        cells of every right-hand side (None: off)."""
+        self._ctx.kxrcf_m = float(m) if m else 0.0
+
+    def kxrcf(self, U, m: float = 1.5):
+        """KXRCF decisions of one state: (flags [nvar, cells] uint8, measure [cells]
+        = max_s |q+ - q-| / <Q>, jumps [cells, 2 d] per-face maxima with the lower
+        face of axis a at 2a and the upper one at 2a + 1)."""
+        U = self._check_U(U)
+        flags = np.empty((self.nvar, self.ncell), dtype=np.uint8)
+        measure = np.empty(self.ncell)
+        jumps = np.empty((self.ncell, 2 * self.d))
+        self._call(self._lib.oracle_kxrcf(C.byref(self._ctx), _ptr(U), float(m), _ptr(flags, C.c_uint8),
+                                          _ptr(measure), _ptr(jumps)))
+        return flags, measure, jumps
+
+    def kxrcf_cells(self, U, cells):
+        """The KXRCF measure max_s |q+ - q-| / <Q> at the listed cells only."""
+        U = self._check_U(U)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty(len(cells))
+        self._call(self._lib.oracle_kxrcf_cells(C.byref(self._ctx), _ptr(U), len(cells), _ptr(cells, C.c_long),
+                                                _ptr(out)))
+        return out
+
+    def kxrcf_threshold(self, m: float = 1.5):
+        """Delta^m, Delta the largest grid spacing."""
+        return max(self._ctx.dx[a] for a in range(self.d)) ** m
 
     def set_flags(self, flags):
         """Replay gate decisions: flags[v][cells] = 1 for WENO, 0 for the linear S0 value."""

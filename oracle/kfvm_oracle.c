@@ -26,6 +26,10 @@
  *      (Harten, Lax and van Leer 1983), with the wavespeed estimates of Batten et
  *      al. (1997) from Roe averages (section 6);
  *   6. Gauss-Legendre face integral of the fluxes and the flux difference.
+ * With the KXRCF indicator on (section 3.5 "Local smoothness indicators" and
+ * the two-pass procedure of section 5.3), step 2 first forms unlimited states
+ * from S0 on every cell and flags the cells whose relative entropy jump across
+ * a face reaches Delta^m (eq. kxrcf); only flagged cells take WENO-AO.
  * The time step is the three-stage SSP Runge-Kutta method of Shu and Osher
  * (1988).  Its stages are written out literally.
  *
@@ -65,6 +69,7 @@ typedef struct {
     int riemann;           /* 0: HLLC, 1: HLL */
     int weno;              /* 1: WENO-AO; 0: linear S0 reconstruction only */
     const uint8_t *flags;  /* optional [nvar][cells]: 1 = WENO, 0 = linear (gate replay) */
+    double kxrcf_m;        /* > 0: the KXRCF indicator with threshold Delta^m picks the WENO cells */
 } oracle_ctx;
 
 /* ---------------------------------------------------------------- grid --- */
@@ -371,20 +376,138 @@ static void face_flux(const oracle_ctx *c, const double *st_lo, const double *st
     }
 }
 
+/* ------------------------------- KXRCF troubled-cell indicator (3.5) --- */
+/* Unlimited Riemann states of one cell, the first pass of section 5.3: the S0
+ * point rows of the table applied to the conserved averages.  (Reconstructing
+ * W = Phi U and mapping back with Phi^-1 gives the same values: the linear
+ * reconstruction commutes with the constant matrix Phi.)  states: [n_pts][nvar]. */
+static void unlimited_states(const oracle_ctx *c, const double *U, long cell, double *states)
+{
+    int nv = c->nvar, np = c->n_pts, N0 = c->mem_ptr[1] - c->mem_ptr[0];
+    const int *mem = c->mem + c->mem_ptr[0];
+    const double *tab = c->w + c->w_ptr[0];
+    for (int i = 0; i < np * nv; ++i) states[i] = 0.0;
+    for (int j = 0; j < N0; ++j) {
+        double u[MAXV];
+        load_cell(c, U, wrap_index(c, cell, c->s0 + mem[j] * c->dim), u);
+        for (int s = 0; s < np; ++s)
+            for (int v = 0; v < nv; ++v) states[s * nv + v] += tab[s * N0 + j] * u[v];
+    }
+}
+
+/* The indicator variable, the entropy q = p / rho^gamma; 0 when u is not admissible. */
+static int entropy(const oracle_ctx *c, const double *u, double *q)
+{
+    if (!admissible(c, u)) return 0;
+    *q = pressure(c, u) / pow(u[0], c->gamma);
+    return 1;
+}
+
+/* Largest |q+ - q-| over the Gauss points of the face with normal a between a
+ * lower cell (states st_lo, its upper face) and its upper neighbour (st_hi, its
+ * lower face); INFINITY when a state is not admissible. */
+static double face_jump(const oracle_ctx *c, const double *st_lo, const double *st_hi, int a)
+{
+    int nv = c->nvar, ng = c->n_pts / (2 * c->dim);
+    double J = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        double qm, qp;
+        if (!entropy(c, st_lo + ((2 * a + 1) * ng + g) * nv, &qm) ||
+            !entropy(c, st_hi + ((2 * a + 0) * ng + g) * nv, &qp))
+            return INFINITY;
+        double j = fabs(qp - qm);
+        if (j > J) J = j;
+    }
+    return J;
+}
+
+/* Left side of eq. kxrcf for one cell: the largest jump over the Gauss points of
+ * all its faces divided by <Q> = p / rho^gamma of its average (INFINITY when a
+ * state involved is not admissible).  jumps (optional): [2 dim] per-face maxima,
+ * the lower face of axis a at 2a, the upper one at 2a + 1. */
+static double kxrcf_measure(const oracle_ctx *c, const double *U, long cell, double *jumps)
+{
+    int nv = c->nvar, np = c->n_pts;
+    double *own = (double *)malloc(sizeof(double) * np * nv * 2), *nb = own + np * nv;
+    double u[MAXV], Q = 0.0, J = 0.0;
+    load_cell(c, U, cell, u);
+    int okQ = entropy(c, u, &Q);
+    unlimited_states(c, U, cell, own);
+    for (int a = 0; a < c->dim; ++a)
+        for (int side = 0; side < 2; ++side) {
+            int off[3] = {0, 0, 0};
+            off[a] = side ? 1 : -1;
+            unlimited_states(c, U, wrap_index(c, cell, off), nb);
+            double j = side ? face_jump(c, own, nb, a) : face_jump(c, nb, own, a);
+            if (jumps) jumps[2 * a + side] = j;
+            if (!(j <= J)) J = j;
+        }
+    free(own);
+    return okQ ? J / Q : INFINITY;
+}
+
+/* Delta^m with Delta the cell width (the largest spacing when they differ) */
+static double kxrcf_threshold(const oracle_ctx *c, double m)
+{
+    double delta = c->dx[0];
+    for (int a = 1; a < c->dim; ++a)
+        if (c->dx[a] > delta) delta = c->dx[a];
+    return pow(delta, m);
+}
+
+/* The cell needs WENO unless eq. kxrcf holds (measure < Delta^m) */
+static uint8_t kxrcf_flag(double measure, double thr) { return !(measure < thr); }
+
+/* KXRCF decisions on the whole grid: flags[nvar][cells] (every variable of a
+ * flagged cell takes WENO-AO); measure (optional) [cells]; jumps (optional)
+ * [cells][2 dim]. */
+int oracle_kxrcf(const oracle_ctx *c, const double *U, double m, uint8_t *flags, double *measure, double *jumps)
+{
+    long N = ncells(c);
+    double thr = kxrcf_threshold(c, m);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long cell = 0; cell < N; ++cell) {
+        double r = kxrcf_measure(c, U, cell, jumps ? jumps + cell * 2 * c->dim : NULL);
+        if (measure) measure[cell] = r;
+        uint8_t f = kxrcf_flag(r, thr);
+        for (int v = 0; v < c->nvar; ++v) flags[v * N + cell] = f;
+    }
+    return OK;
+}
+
+/* KXRCF measure (left side of eq. kxrcf) at a list of cells only, for spot
+ * checks on grids too large for the whole-grid routine.  measure: [count]. */
+int oracle_kxrcf_cells(const oracle_ctx *c, const double *U, long count, const long *cells, double *measure)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < count; ++i) measure[i] = kxrcf_measure(c, U, cells[i], NULL);
+    return OK;
+}
+
 /* ----------------------------------------------------------- exported --- */
 /* All Riemann states: states[cell][n_pts][nvar]. */
 int oracle_states(const oracle_ctx *c, const double *U, double *states)
 {
     long N = ncells(c);
     int err = OK;
+    /* two-pass procedure (section 5.3): the indicator's flags select WENO-AO */
+    oracle_ctx cc = *c;
+    uint8_t *fl = NULL;
+    if (c->kxrcf_m > 0.0) {
+        fl = (uint8_t *)malloc((size_t)N * c->nvar);
+        if (!fl) return ERR_ARG;
+        oracle_kxrcf(c, U, c->kxrcf_m, fl, NULL, NULL);
+        cc.flags = fl;
+    }
 #pragma omp parallel for schedule(dynamic, 64)
     for (long cell = 0; cell < N; ++cell) {
-        int e = cell_states(c, U, cell, states + cell * c->n_pts * c->nvar);
+        int e = cell_states(&cc, U, cell, states + cell * c->n_pts * c->nvar);
         if (e != OK) {
 #pragma omp atomic write
             err = e;
         }
     }
+    free(fl);
     return err;
 }
 
@@ -420,6 +543,33 @@ int oracle_rhs(const oracle_ctx *c, const double *U, double *dUdt)
 int oracle_rhs_cells(const oracle_ctx *c, const double *U, long count, const long *cells, double *out)
 {
     int nv = c->nvar, np = c->n_pts, err = OK;
+    long N = ncells(c);
+    /* with the indicator on, the flags of every cell whose states enter (each
+     * sampled cell and its face neighbours) */
+    oracle_ctx cc = *c;
+    uint8_t *fl = NULL;
+    if (c->kxrcf_m > 0.0) {
+        fl = (uint8_t *)calloc((size_t)N * nv, 1);
+        if (!fl) return ERR_ARG;
+        double thr = kxrcf_threshold(c, c->kxrcf_m);
+        long nneed = count * (2 * c->dim + 1);
+        long *target = (long *)malloc(sizeof(long) * nneed);
+        uint8_t *f = (uint8_t *)malloc(nneed);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (long k = 0; k < nneed; ++k) {
+            long cell = cells[k / (2 * c->dim + 1)];
+            int r = (int)(k % (2 * c->dim + 1)), off[3] = {0, 0, 0};
+            if (r > 0) off[(r - 1) / 2] = (r - 1) % 2 ? 1 : -1;
+            target[k] = wrap_index(c, cell, off);
+            f[k] = kxrcf_flag(kxrcf_measure(c, U, target[k], NULL), thr);
+        }
+        for (long k = 0; k < nneed; ++k)
+            for (int v = 0; v < nv; ++v) fl[v * N + target[k]] = f[k];
+        free(target);
+        free(f);
+        cc.flags = fl;
+    }
+    c = &cc;
 #pragma omp parallel for schedule(dynamic, 1)
     for (long i = 0; i < count; ++i) {
         long cell = cells[i];
@@ -444,6 +594,7 @@ int oracle_rhs_cells(const oracle_ctx *c, const double *U, long count, const lon
         for (int v = 0; v < nv; ++v) out[i * nv + v] = acc[v];
         free(st);
     }
+    free(fl);
     return err;
 }
 
