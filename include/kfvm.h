@@ -51,6 +51,7 @@ enum {
 
 enum { KFVM_FP64 = 0, KFVM_SPLIT_F16 = 1, KFVM_SPLIT_BF16 = 2 };   /* kfvm_set_precision */
 enum { KFVM_HLLC = 0, KFVM_HLL = 1 };                              /* kfvm_set_riemann */
+enum { KFVM_IND_NONE = 0, KFVM_IND_KXRCF = 1 };                    /* kfvm_set_indicator */
 
 typedef struct kfvm_ctx kfvm_ctx;
 
@@ -128,7 +129,7 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
  * nonlinear-weight normalisation, the limiter, the Riemann solver and the
  * Runge-Kutta update stay in float64.  The split modes need fewer than 2^30
- * cells and are not available for 3D order 7 (KFVM_ERR_ARG). */
+ * cells (KFVM_ERR_ARG otherwise). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 
 /* Positivity limiter of section 4 with flattener eta = 0: enabled != 0 turns it
@@ -165,8 +166,37 @@ int kfvm_weights_size(int dim, int R);
  * flags[nvar][ncells] of bytes: nonzero = WENO-AO (section 3.2), 0 = the linear
  * full-stencil value (what a troubled-cell gate decides; section 3.5 describes
  * the paper's own indicator).  NULL (the default) = WENO-AO everywhere.  The
- * array must stay valid while work that reads it is queued. */
+ * array must stay valid while work that reads it is queued.  A non-NULL array
+ * turns the gate and the indicator off. */
 int kfvm_set_flags(kfvm_ctx *ctx, const uint8_t *flags);
+
+/* ---- KXRCF troubled-cell indicator (section 3.5, eq. kxrcf) ----------------
+ * The two-pass Riemann-state procedure of section 5.3.  First pass: unlimited
+ * states from the full stencil S0 (its face-point rows applied to the conserved
+ * averages) at the Gauss points of every face, from both sides.  A cell takes
+ * the linear S0 value for all its variables when
+ *     max_s |q+_s - q-_s| / <Q>  <  Delta^m,
+ * s over the Gauss points of its 2 dim faces, q = p / rho^gamma of the state
+ * from the cell (-) and from the neighbour across the face (+), <Q> the same of
+ * the cell's average, Delta the cell width (the largest dx); otherwise WENO-AO
+ * for all its variables.  A cell whose average or any of those point states has
+ * rho <= 0 or p <= 0 is flagged.  The first pass runs in float64 in either
+ * precision mode. */
+
+/* kind = KFVM_IND_KXRCF: every subsequent kfvm_rhs, kfvm_step stage and
+ * kfvm_face_states runs the indicator on its input and reconstructs with its
+ * decisions; m > 0 is the power of Delta (the paper uses 3/2).  Turns the gate
+ * and kfvm_set_flags off.  KFVM_IND_NONE (the default) turns it off.  Allocates
+ * dim * ncells float64 of jumps and nvar * ncells bytes of flags on first use. */
+int kfvm_set_indicator(kfvm_ctx *ctx, int kind, double m);
+
+/* Run the indicator once on U with power m: jumps[dim][ncells] float64 (optional
+ * device buffer) receives, per axis a, the largest |q+ - q-| over the Gauss points
+ * of each cell's upper face along a (infinity where a state is not admissible);
+ * flags[nvar][ncells] bytes (optional device buffer) the decisions, 1 = WENO-AO.
+ * With NULL outputs the context's own buffers receive them (kfvm_get_flags
+ * reads the flags).  Asynchronous. */
+int kfvm_kxrcf(kfvm_ctx *ctx, const double *U, double m, double *jumps, uint8_t *flags);
 
 /* ---- learned troubled-cell gate -------------------------------------------
  * A small network decides per (variable, cell) whether the WENO-AO machinery
@@ -193,8 +223,9 @@ int kfvm_mlp_sizes(int dim, int *n_in, int *n_params);
  * disables it.  Clears kfvm_set_flags. */
 int kfvm_set_gate(kfvm_ctx *ctx, const float *params, float threshold);
 
-/* Copy the gate's decisions of the last reconstruction, flags[nvar][ncells]
- * bytes (1 = WENO-AO), to a device buffer (asynchronous). */
+/* Copy the decisions of the last gated or indicator-driven reconstruction (or
+ * of the last kfvm_kxrcf without a flags buffer), flags[nvar][ncells] bytes
+ * (1 = WENO-AO), to a device buffer (asynchronous). */
 int kfvm_get_flags(kfvm_ctx *ctx, uint8_t *flags);
 
 /* Training samples from state U: x[nvar][ncells][n_in] float32 gate inputs and
@@ -218,8 +249,9 @@ int kfvm_set_timing(kfvm_ctx *ctx, int on);
 
 /* Synchronise; write the summed device time in milliseconds and the launch
  * count of each kernel class since the last call (index 0: reconstruction,
- * 1: face flux, 2: flux difference and stage update) into ms[n], launches[n]
- * (n >= 3), and forget the recorded events. */
+ * 1: face flux, 2: flux difference and stage update, 3: the KXRCF indicator's
+ * first pass and flags) into ms[n], launches[n] (n >= 4), and forget the
+ * recorded events. */
 int kfvm_kernel_times(kfvm_ctx *ctx, double *ms, long long *launches, int n);
 
 /* Message of the last error on this context (never NULL). */

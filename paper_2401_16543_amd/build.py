@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libkfvm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["api.hip", "rhs_fp64.hip", "rhs_mixed.hip", "mlp.hip"]
+HIP_SOURCES = ["api.hip", "rhs_fp64.hip", "rhs_mixed.hip", "kxrcf.hip", "mlp.hip"]
 CXX_SOURCES = ["weights.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

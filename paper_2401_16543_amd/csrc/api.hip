@@ -44,6 +44,11 @@ struct kfvm_ctx {
     // gate-network training workspace
     float *d_mlp_ws = nullptr;
     size_t mlp_ws_floats = 0;
+    // KXRCF indicator (two-pass reconstruction)
+    int indicator = KFVM_IND_NONE;
+    double kx_m = 1.5;
+    double *d_kx_w = nullptr;       // S0 face rows as [axis][side][member][Gauss point]
+    double *d_kx_jump = nullptr;    // [dim][ncell] largest entropy jump on each upper face
 };
 
 namespace {
@@ -364,18 +369,90 @@ static int ensure_face64(kfvm_ctx *c)
     return alloc(c, (void **)&c->work.face, sizeof(double) * (size_t)npts_of(c->dim, c->R) * c->nvar * c->geom.ncell);
 }
 
+// The KXRCF operands: the S0 face-point rows regrouped per (axis, side) so that
+// the rows one thread needs for a member are contiguous, and the buffers of
+// the indicator's output.
+extern "C++" template <int D, int R>
+static void kxrcf_rows(const double *tab, std::vector<double> &kw)
+{
+    using S = kfvm::Stencil<D, R>;
+    constexpr int N0 = S::N0, NG = S::NG;
+    kw.assign((size_t)kfvm::kxrcf_table_size(D, R), 0.0);
+    for (int a = 0; a < D; ++a)
+        for (int side = 0; side < 2; ++side)
+            for (int j = 0; j < N0; ++j)
+                for (int p = 0; p < NG; ++p) {
+                    // side 0: the cell's upper face (2a + 1); side 1: the neighbour's lower face (2a)
+                    const int row = (2 * a + (side == 0 ? 1 : 0)) * NG + p;
+                    kw[((size_t)(a * 2 + side) * N0 + j) * NG + p] = tab[row * N0 + j];   // stencil 0 leads the tables
+                }
+}
+
+static int ensure_kxrcf(kfvm_ctx *c)
+{
+    if (!c->d_kx_w) {
+        std::vector<double> kw;
+        if (c->dim == 2 && c->R == 2) kxrcf_rows<2, 2>(c->host_tables.data(), kw);
+        else if (c->dim == 2 && c->R == 3) kxrcf_rows<2, 3>(c->host_tables.data(), kw);
+        else if (c->dim == 3 && c->R == 2) kxrcf_rows<3, 2>(c->host_tables.data(), kw);
+        else kxrcf_rows<3, 3>(c->host_tables.data(), kw);
+        int rc = alloc(c, (void **)&c->d_kx_w, sizeof(double) * kw.size());
+        if (rc != KFVM_OK) return rc;
+        HIP_TRY(c, hipMemcpy(c->d_kx_w, kw.data(), sizeof(double) * kw.size(), hipMemcpyHostToDevice));
+    }
+    if (!c->d_kx_jump) {
+        const int rc = alloc(c, (void **)&c->d_kx_jump, sizeof(double) * (size_t)c->dim * c->geom.ncell);
+        if (rc != KFVM_OK) return rc;
+    }
+    if (!c->d_flags_out) return alloc(c, (void **)&c->d_flags_out, (size_t)c->nvar * c->geom.ncell);
+    return KFVM_OK;
+}
+
+// Delta^m, Delta the cell width (the largest spacing when they differ)
+static double kxrcf_threshold(const kfvm_ctx *c, double m)
+{
+    double delta = c->geom.dx[0];
+    for (int a = 1; a < c->dim; ++a) delta = std::fmax(delta, c->geom.dx[a]);
+    return std::pow(delta, m);
+}
+
+static int run_kxrcf(kfvm_ctx *c, const double *U, double m, double *J, uint8_t *flags)
+{
+    kfvm::Timing tm = timing_of(c);
+    if (tm.on) tm.record(tm.self, kfvm::KT_INDICATOR, c->stream, 1);
+    hipError_t e = kfvm::launch_kxrcf(c->dim, c->R, c->geom, c->d_kx_w, U, J, flags, kxrcf_threshold(c, m), c->stream);
+    if (tm.on) tm.record(tm.self, kfvm::KT_INDICATOR, c->stream, 0);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    return KFVM_OK;
+}
+
+// The reconstruction's per-(variable, cell) choices for input U: with the KXRCF
+// indicator on, its first pass runs here and its flags replace any others.
+static int prepare_flags(kfvm_ctx *c, const double *U, kfvm::Work &w)
+{
+    w = c->work;
+    if (c->indicator != KFVM_IND_KXRCF) return KFVM_OK;
+    const int rc = run_kxrcf(c, U, c->kx_m, c->d_kx_jump, c->d_flags_out);
+    w.flags_in = c->d_flags_out;
+    return rc;
+}
+
 static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
 {
     hipError_t e;
+    kfvm::Work w;
+    int rc = prepare_flags(c, Uin, w);
+    if (rc != KFVM_OK) return rc;
     if (c->precision == KFVM_FP64) {
-        const int rc = ensure_face64(c);
+        rc = ensure_face64(c);
         if (rc != KFVM_OK) return rc;
+        w.face = c->work.face;
         kfvm::Tables t{c->d_tables, c->d_wch};
-        e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, c->work, c->lim, c->riemann, U0, Uin, out, stage, dt,
+        e = kfvm::launch_rhs_fp64(c->dim, c->R, c->geom, t, w, c->lim, c->riemann, U0, Uin, out, stage, dt,
                                   c->stream, timing_of(c));
     } else {
         kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
-        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
+        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, w, c->lim,
                                    c->riemann, U0, Uin, out, stage, dt, nullptr, c->stream, timing_of(c), gate_of(c));
     }
     if (e != hipSuccess) return hip_fail(c, e, "launch");
@@ -487,14 +564,18 @@ int kfvm_face_states(kfvm_ctx *c, const double *U, double *states)
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     if (!U || !states) return fail(c, KFVM_ERR_ARG, "null buffer");
     hipError_t e;
+    kfvm::Work w;
+    int rc = prepare_flags(c, U, w);
+    if (rc != KFVM_OK) return rc;
     if (c->precision == KFVM_FP64) {
-        const int rc = ensure_face64(c);
+        rc = ensure_face64(c);
         if (rc != KFVM_OK) return rc;
+        w.face = c->work.face;
         kfvm::Tables t{c->d_tables, c->d_wch};
-        e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, c->work, c->lim, U, states, c->stream);
+        e = kfvm::launch_face_states(c->dim, c->R, c->geom, t, w, c->lim, U, states, c->stream);
     } else {
         kfvm::MixTables t{c->d_mix_full, c->d_mix_lin, c->mix_sw};
-        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, c->work, c->lim,
+        e = kfvm::launch_rhs_mixed(c->dim, c->R, c->precision == KFVM_SPLIT_BF16, c->geom, t, w, c->lim,
                                    c->riemann, U, U, nullptr, 0, 0.0, states, c->stream, kfvm::Timing{0, nullptr, nullptr},
                                    gate_of(c));
     }
@@ -506,8 +587,39 @@ int kfvm_set_flags(kfvm_ctx *c, const uint8_t *flags)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     c->work.flags_in = flags;
-    if (flags) c->gate_on = 0;
+    if (flags) {
+        c->gate_on = 0;
+        c->indicator = KFVM_IND_NONE;
+    }
     return KFVM_OK;
+}
+
+int kfvm_set_indicator(kfvm_ctx *c, int kind, double m)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (kind != KFVM_IND_NONE && kind != KFVM_IND_KXRCF) return fail(c, KFVM_ERR_ARG, "unknown indicator");
+    if (kind == KFVM_IND_NONE) {
+        c->indicator = KFVM_IND_NONE;
+        return KFVM_OK;
+    }
+    if (!(m > 0.0) || !std::isfinite(m)) return fail(c, KFVM_ERR_ARG, "m must be positive and finite");
+    const int rc = ensure_kxrcf(c);
+    if (rc != KFVM_OK) return rc;
+    c->indicator = kind;
+    c->kx_m = m;
+    c->gate_on = 0;
+    c->work.flags_in = nullptr;
+    return KFVM_OK;
+}
+
+int kfvm_kxrcf(kfvm_ctx *c, const double *U, double m, double *jumps, uint8_t *flags)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U) return fail(c, KFVM_ERR_ARG, "null buffer");
+    if (!(m > 0.0) || !std::isfinite(m)) return fail(c, KFVM_ERR_ARG, "m must be positive and finite");
+    const int rc = ensure_kxrcf(c);
+    if (rc != KFVM_OK) return rc;
+    return run_kxrcf(c, U, m, jumps ? jumps : c->d_kx_jump, flags ? flags : c->d_flags_out);
 }
 
 int kfvm_mlp_sizes(int dim, int *n_in, int *n_params)
@@ -556,7 +668,7 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
     if (!c->d_gate_w) {
         int rc = alloc(c, (void **)&c->d_gate_w, w.size() * 2);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_gate_vec, sizeof(float) * 97);
-        if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_flags_out, (size_t)c->nvar * c->geom.ncell);
+        if (rc == KFVM_OK && !c->d_flags_out) rc = alloc(c, (void **)&c->d_flags_out, (size_t)c->nvar * c->geom.ncell);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_gate_raw, (size_t)c->geom.ncell);
         if (rc != KFVM_OK) return rc;
     }
@@ -565,6 +677,7 @@ int kfvm_set_gate(kfvm_ctx *c, const float *params, float threshold)
     c->gate_thr = threshold;
     c->gate_on = 1;
     c->work.flags_in = nullptr;
+    c->indicator = KFVM_IND_NONE;
     return KFVM_OK;
 }
 
@@ -572,7 +685,7 @@ int kfvm_get_flags(kfvm_ctx *c, uint8_t *flags)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
     if (!flags) return fail(c, KFVM_ERR_ARG, "null buffer");
-    if (!c->d_flags_out) return fail(c, KFVM_ERR_STATE, "no gate has run");
+    if (!c->d_flags_out) return fail(c, KFVM_ERR_STATE, "neither the gate nor the indicator has run");
     HIP_TRY(c, hipMemcpyAsync(flags, c->d_flags_out, (size_t)c->nvar * c->geom.ncell, hipMemcpyDeviceToDevice,
                               c->stream));
     return KFVM_OK;

@@ -48,7 +48,7 @@ constexpr int FP64_CHUNK = 8;    // members per chunk of the chunked FP64 recons
 
 // Optional per-kernel timing: when `on`, every launch is bracketed by HIP events
 // on the launch stream; the host sums the elapsed times later.
-enum { KT_RECON = 0, KT_FLUX = 1, KT_UPDATE = 2, KT_COUNT = 3 };
+enum { KT_RECON = 0, KT_FLUX = 1, KT_UPDATE = 2, KT_INDICATOR = 3, KT_COUNT = 4 };
 struct Timing {
     int on;
     void (*record)(void *self, int kind, hipStream_t s, int begin);
@@ -86,6 +86,14 @@ hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, co
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s);
+
+// KXRCF indicator (kxrcf.hip): jumps J[dim][ncell] of the upper faces, then
+// (flags != nullptr) flags[nvar][ncell] = 1 where eq. kxrcf fails for threshold thr.
+// kw: the S0 face-point rows laid out [axis][side][member][Gauss point], side 0
+// the upper face of the cell, side 1 the lower face of its upper neighbour.
+int kxrcf_table_size(int dim, int R);
+hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags,
+                        double thr, hipStream_t s);
 
 // gate network: training and sample export (mlp.hip)
 int mlp_n_in(int dim);

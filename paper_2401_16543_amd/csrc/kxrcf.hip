@@ -1,0 +1,211 @@
+// KXRCF troubled-cell indicator (section 3.5, eq. kxrcf) for gfx950, FP64: the
+// first pass of the two-pass Riemann-state procedure of section 5.3.
+//
+//   jump   one thread per cell.  The workgroup stages its tile of conserved
+//          averages in LDS with a periodic halo of R cells below and R + 1
+//          above (the upper neighbour's stencil).  Per axis the thread forms the
+//          unlimited states (the S0 point rows applied to the conserved averages
+//          themselves) at the Gauss points of the face it shares with its upper
+//          neighbour, from both sides in turn: its own upper-face rows over its
+//          S0, then the neighbour's lower-face rows over the neighbour's S0.  Each
+//          average read from LDS feeds the n_g point accumulators of that side;
+//          the weights are uniform across the wave (scalar loads from a table
+//          laid out [axis][side][member][point]).  The face keeps the largest
+//          |q+ - q-| of the entropy q = p / rho^gamma, or infinity when a state
+//          is not admissible.
+//   flags  one thread per cell: the largest jump over its 2d faces against
+//          Delta^m times the entropy of its own average.  Every variable of a
+//          flagged cell takes WENO-AO in the reconstruction that follows, the
+//          other cells the linear S0 value.
+#include "device_common.hpp"
+
+namespace kfvm {
+namespace {
+using namespace dev;
+
+template <int D, int R>
+struct KxCfg {
+    using S = Stencil<D, R>;
+    static constexpr S st{};
+    static constexpr int TX = D == 2 ? 16 : 8;
+    static constexpr int TY = D == 2 ? 16 : 8;
+    static constexpr int TZ = D == 2 ? 1 : 4;
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int HX = TX + 2 * R + 1, HY = TY + 2 * R + 1, HZ = D == 3 ? TZ + 2 * R + 1 : 1;
+    static constexpr int HN = HX * HY * HZ;
+    static constexpr int NV = D + 2, NG = S::NG, N0 = S::N0;
+    static constexpr int MG = 2;     // members per group of LDS reads
+};
+
+// q = p / rho^gamma of a point state; false when the state is not admissible
+template <int D>
+__device__ __forceinline__ bool point_entropy(const double *u, double gam, double &q)
+{
+    if (!admissible<D>(u, gam)) return false;
+    q = pressure<D>(u, gam) * pow(u[0], -gam);
+    return true;
+}
+
+template <int D, int R>
+__global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *__restrict__ U,
+                                                                const double *__restrict__ kw,
+                                                                double *__restrict__ J, Geom g)
+{
+    using C = KxCfg<D, R>;
+    constexpr int NV = C::NV, NG = C::NG, N0 = C::N0, MG = C::MG;
+    __shared__ double tile[NV][C::HN];
+
+    const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
+    const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
+    const long nblk = (long)nbx * nby * nbz;
+    const long t = xcd_tile(blockIdx.x, nblk);
+    if (t >= nblk) return;
+    const int bx = (int)(t % nbx), by = (int)((t / nbx) % nby), bz = (int)(t / ((long)nbx * nby));
+    const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+
+    // one conditional wrap reaches every halo index once each axis holds a tile
+    // plus R + 1 cells; smaller grids take the full modulo
+    const bool near = g.n[0] >= C::TX + R + 1 && g.n[1] >= C::TY + R + 1 && (D == 2 || g.n[2] >= C::TZ + R + 1);
+    for (int i = threadIdx.x; i < C::HN; i += C::NT) {
+        const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+        const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
+        const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
+        const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
+        const long cell = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[v][i] = U[v * g.ncell + cell];
+    }
+    __syncthreads();
+
+    const int tx = threadIdx.x % C::TX, ty = (threadIdx.x / C::TX) % C::TY, tz = threadIdx.x / (C::TX * C::TY);
+    const int cx = bx * C::TX + tx, cy = by * C::TY + ty, cz = D == 3 ? bz * C::TZ + tz : 0;
+    if (cx >= g.n[0] || cy >= g.n[1] || (D == 3 && cz >= g.n[2])) return;
+    const long cell = cx + (long)g.n[0] * (cy + (long)g.n[1] * cz);
+    const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
+    const double gam = g.gamma;
+
+#pragma unroll 1
+    for (int a = 0; a < D; ++a) {
+        const int step = a == 0 ? 1 : (a == 1 ? C::HX : C::HX * C::HY);
+        double q0[NG], jmax = 0.0;
+        bool bad = false;
+        // side 0: this cell, rows of its upper face along a; side 1: the upper
+        // neighbour, rows of its lower face (the same physical points)
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            const double *wk = kw + (long)(a * 2 + side) * N0 * NG;
+            int base = lc + side * step;
+            asm volatile("" : "+v"(base));
+            double acc[NG][NV];
+#pragma unroll
+            for (int p = 0; p < NG; ++p)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[p][v] = 0.0;
+            // members in groups of MG: the group's LDS reads, then its FMAs; the
+            // accumulators are pinned after each group and the next group's LDS
+            // index depends on them (empty asm), so the reads of one group are
+            // in flight at a time instead of all N0 x NV hoisted up front
+#pragma unroll
+            for (int j0 = 0; j0 < N0; j0 += MG) {
+                double u[MG][NV];
+#pragma unroll
+                for (int m = 0; m < MG; ++m) {
+                    const int j = j0 + m < N0 ? j0 + m : N0 - 1;
+                    const int o = base + C::st.off[j][0] + C::HX * (C::st.off[j][1] + C::HY * C::st.off[j][2]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) u[m][v] = tile[v][o];
+                }
+#pragma unroll
+                for (int m = 0; m < MG; ++m) {
+                    if (j0 + m >= N0) break;
+#pragma unroll
+                    for (int p = 0; p < NG; ++p) {
+                        const double w = wk[(j0 + m) * NG + p];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[p][v] = fma(w, u[m][v], acc[p][v]);
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < NG; ++p) {
+                    if constexpr (NV == 4)
+                        asm volatile("" : "+v"(acc[p][0]), "+v"(acc[p][1]), "+v"(acc[p][2]), "+v"(acc[p][3]));
+                    else
+                        asm volatile("" : "+v"(acc[p][0]), "+v"(acc[p][1]), "+v"(acc[p][2]), "+v"(acc[p][3]),
+                                     "+v"(acc[p][4]));
+                }
+                asm volatile("" : "+v"(base) : "v"(acc[NG - 1][NV - 1]));
+            }
+#pragma unroll
+            for (int p = 0; p < NG; ++p) {
+                double q = 0.0;
+                bad = bad || !point_entropy<D>(acc[p], gam, q);
+                if (side == 0) q0[p] = q;
+                else jmax = fmax(jmax, fabs(q - q0[p]));
+            }
+        }
+        J[(long)a * g.ncell + cell] = bad ? INFINITY : jmax;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_kxrcf_flags(const double *__restrict__ U, const double *__restrict__ J,
+                                                   uint8_t *__restrict__ flags, Geom g, double thr)
+{
+    constexpr int NV = D + 2;
+    const long cell = (long)blockIdx.x * 256 + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const int c[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+    const long stride[3] = {1, g.n[0], (long)g.n[0] * g.n[1]};
+    double jm = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const long lower = cell + (c[a] == 0 ? (long)(g.n[a] - 1) * stride[a] : -stride[a]);
+        jm = fmax(jm, fmax(J[(long)a * g.ncell + cell], J[(long)a * g.ncell + lower]));
+    }
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + cell];
+    double Q = 0.0;
+    const bool ok = point_entropy<D>(u, g.gamma, Q);
+    // smooth (linear S0 value) only when eq. kxrcf holds: jump / <Q> < Delta^m
+    const uint8_t f = (ok && jm < thr * Q) ? 0 : 1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) flags[(long)v * g.ncell + cell] = f;
+}
+
+template <int D, int R>
+hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags, double thr,
+                      hipStream_t s)
+{
+    using C = KxCfg<D, R>;
+    const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
+                      (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
+    hipLaunchKernelGGL((k_kxrcf_jump<D, R>), dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(C::NT), 0, s, U, kw, J, g);
+    if (flags)
+        hipLaunchKernelGGL((k_kxrcf_flags<D>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, U, J, flags,
+                           g, thr);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int kxrcf_table_size(int dim, int R)
+{
+    if (dim == 2 && R == 2) return 2 * 2 * Stencil<2, 2>::N0 * Stencil<2, 2>::NG;
+    if (dim == 2 && R == 3) return 2 * 2 * Stencil<2, 3>::N0 * Stencil<2, 3>::NG;
+    if (dim == 3 && R == 2) return 3 * 2 * Stencil<3, 2>::N0 * Stencil<3, 2>::NG;
+    if (dim == 3 && R == 3) return 3 * 2 * Stencil<3, 3>::N0 * Stencil<3, 3>::NG;
+    return -1;
+}
+
+hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags,
+                        double thr, hipStream_t s)
+{
+    if (dim == 2 && R == 2) return kxrcf_impl<2, 2>(g, kw, U, J, flags, thr, s);
+    if (dim == 2 && R == 3) return kxrcf_impl<2, 3>(g, kw, U, J, flags, thr, s);
+    if (dim == 3 && R == 2) return kxrcf_impl<3, 2>(g, kw, U, J, flags, thr, s);
+    if (dim == 3 && R == 3) return kxrcf_impl<3, 3>(g, kw, U, J, flags, thr, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace kfvm

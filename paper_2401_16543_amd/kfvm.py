@@ -22,9 +22,10 @@ EXPORTED = [
     "kfvm_set_limiter", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
-    "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step",
+    "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step", "kfvm_set_indicator", "kfvm_kxrcf",
 ]
-KERNEL_CLASSES = ("recon", "flux", "update")
+KERNEL_CLASSES = ("recon", "flux", "update", "indicator")
+KFVM_IND_NONE, KFVM_IND_KXRCF = 0, 1
 
 
 class KfvmError(RuntimeError):
@@ -85,6 +86,8 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_gate_samples": ([vp, vp, vp, vp], ip),
         "kfvm_mlp_train_step": ([vp, vp, vp, ip, vp, vp, vp, ip, C.c_float, C.c_float, vp, vp, vp], ip),
         "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
+        "kfvm_set_indicator": ([vp, ip, C.c_double], ip),
+        "kfvm_kxrcf": ([vp, vp, C.c_double, vp, vp], ip),
         "kfvm_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -243,6 +246,23 @@ class KFVM:
         self._flags = flags
         self._check(self.lib.kfvm_set_flags(self._h, C.c_void_p(flags.data_ptr())))
 
+    # -- KXRCF indicator -------------------------------------------------------
+    def set_indicator(self, kind, m: float = 1.5):
+        """kind: "kxrcf" (the two-pass reconstruction with threshold Delta^m) or None."""
+        self._check(self.lib.kfvm_set_indicator(self._h, {None: KFVM_IND_NONE, "kxrcf": KFVM_IND_KXRCF}[kind],
+                                                float(m)))
+
+    def kxrcf(self, U, m: float = 1.5):
+        """One pass of the indicator on U: (jumps [dim, ncell] float64 of the upper
+        faces, flags [nvar, ncell] uint8, 1 = WENO-AO)."""
+        ncell = U[0].numel()
+        jumps = torch.empty((self.dim, ncell), dtype=torch.float64, device=U.device)
+        flags = torch.empty((self.nvar, ncell), dtype=torch.uint8, device=U.device)
+        self._stream()
+        self._check(self.lib.kfvm_kxrcf(self._h, self._state(U), float(m), C.c_void_p(jumps.data_ptr()),
+                                        C.c_void_p(flags.data_ptr())))
+        return jumps, flags
+
     # -- learned gate ------------------------------------------------------------
     def mlp_sizes(self):
         n_in, n_p = C.c_int(), C.c_int()
@@ -297,9 +317,10 @@ class KFVM:
 
     def kernel_times(self) -> dict:
         """{kernel class: (total ms, launches)} since the last call."""
-        ms = (C.c_double * 3)()
-        n = (C.c_longlong * 3)()
-        self._check(self.lib.kfvm_kernel_times(self._h, ms, n, 3))
+        k = len(KERNEL_CLASSES)
+        ms = (C.c_double * k)()
+        n = (C.c_longlong * k)()
+        self._check(self.lib.kfvm_kernel_times(self._h, ms, n, k))
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
     def stats(self) -> dict:
