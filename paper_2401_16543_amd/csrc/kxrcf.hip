@@ -12,7 +12,11 @@
 //          the weights are uniform across the wave (scalar loads from a table
 //          laid out [axis][side][member][point]).  The face keeps the largest
 //          |q+ - q-| of the entropy q = p / rho^gamma, or infinity when a state
-//          is not admissible.
+//          is not admissible.  Both sides' q are formed as p (rho / rho_c)^-gamma
+//          with rho_c the cell's average density, by a binomial series when
+//          rho is within 1/32 of rho_c (pow otherwise), and the face maximum is
+//          scaled by rho_c^-gamma once.  Reads of a member group are issued one
+//          group ahead of the FMAs that use them.
 //   flags  one thread per cell: the largest jump over its 2d faces against
 //          Delta^m times the entropy of its own average.  Every variable of a
 //          flagged cell takes WENO-AO in the reconstruction that follows, the
@@ -23,18 +27,27 @@ namespace kfvm {
 namespace {
 using namespace dev;
 
+constexpr int KX_SERIES_K = 15;
+struct KxSeries {
+    double a[KX_SERIES_K];   // a_k = (1 - k - gamma) / k
+    double xmax;             // 1/32 for gamma <= 10, else -1 (pow everywhere)
+};
+
 template <int D, int R>
 struct KxCfg {
     using S = Stencil<D, R>;
     static constexpr S st{};
-    static constexpr int TX = D == 2 ? 16 : 8;
+    // 3D order 7: a wider tile (512 threads, 152 KB of LDS) for a better halo
+    // ratio and two waves per SIMD
+    static constexpr int TX = D == 2 ? 16 : (R == 3 ? 16 : 8);
     static constexpr int TY = D == 2 ? 16 : 8;
     static constexpr int TZ = D == 2 ? 1 : 4;
     static constexpr int NT = TX * TY * TZ;
     static constexpr int HX = TX + 2 * R + 1, HY = TY + 2 * R + 1, HZ = D == 3 ? TZ + 2 * R + 1 : 1;
     static constexpr int HN = HX * HY * HZ;
     static constexpr int NV = D + 2, NG = S::NG, N0 = S::N0;
-    static constexpr int MG = 2;     // members per group of LDS reads
+    static constexpr int MG = NG >= 9 ? 1 : 2;   // members per group of reads
+    static constexpr bool PIN_W = NG * MG <= 8;   // two groups of weights fit the scalar registers
 };
 
 // q = p / rho^gamma of a point state; false when the state is not admissible
@@ -46,10 +59,35 @@ __device__ __forceinline__ bool point_entropy(const double *u, double gam, doubl
     return true;
 }
 
+// (1 + x)^-gamma for |x| <= 1/32 by its binomial series, nested as
+// 1 + a_1 x (1 + a_2 x (1 + ... (1 + a_K x))), a_k = (1 - k - gamma) / k: for
+// gamma <= 10 the first omitted term is below 2e-18.
+__device__ __forceinline__ double binomial_pow(double x, const KxSeries &ser)
+{
+    double t = 1.0;
+#pragma unroll
+    for (int k = KX_SERIES_K; k >= 1; --k) t = fma(ser.a[k - 1] * x, t, 1.0);
+    return t;
+}
+
+// q / rho_ref^-gamma = p (rho / rho_ref)^-gamma of a point state; false when the
+// state is not admissible.  The series covers densities within 1/32 of the
+// reference (every point of smooth data), pow the rest.
+template <int D>
+__device__ __forceinline__ bool scaled_entropy(const double *u, double gam, double irho_ref, const KxSeries &ser,
+                                               double &q)
+{
+    if (!admissible<D>(u, gam)) return false;
+    const double r = u[0] * irho_ref, x = r - 1.0;
+    const double y = fabs(x) <= ser.xmax ? binomial_pow(x, ser) : pow(r, -gam);
+    q = pressure<D>(u, gam) * y;
+    return true;
+}
+
 template <int D, int R>
 __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *__restrict__ U,
                                                                 const double *__restrict__ kw,
-                                                                double *__restrict__ J, Geom g)
+                                                                double *__restrict__ J, Geom g, KxSeries ser)
 {
     using C = KxCfg<D, R>;
     constexpr int NV = C::NV, NG = C::NG, N0 = C::N0, MG = C::MG;
@@ -83,6 +121,10 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
     const long cell = cx + (long)g.n[0] * (cy + (long)g.n[1] * cz);
     const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
     const double gam = g.gamma;
+    // the entropies of both sides are formed relative to this cell's average
+    // density and scaled back once per cell
+    const double rho_ref = tile[0][lc], irho_ref = rcp64(rho_ref);
+    const double qscale = rho_ref > 0.0 ? pow(rho_ref, -gam) : 0.0;
 
 #pragma unroll 1
     for (int a = 0; a < D; ++a) {
@@ -101,29 +143,50 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
             for (int p = 0; p < NG; ++p)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) acc[p][v] = 0.0;
-            // members in groups of MG: the group's LDS reads, then its FMAs; the
-            // accumulators are pinned after each group and the next group's LDS
-            // index depends on them (empty asm), so the reads of one group are
-            // in flight at a time instead of all N0 x NV hoisted up front
-#pragma unroll
-            for (int j0 = 0; j0 < N0; j0 += MG) {
-                double u[MG][NV];
+            // Members in groups of MG, software-pipelined: the LDS reads and the
+            // weight loads (scalar) of group k + 1 are issued before the FMAs of
+            // group k, and the weights are pinned only after those FMAs, which is
+            // where the wave waits for both.  After each group's FMAs the
+            // accumulators are pinned too and the LDS index of the reads that
+            // follow depends on them (empty asm), so at most two groups' values
+            // are live instead of all N0 x NV reads hoisted up front.
+            double u[2][MG][NV], wb[2][MG][NG];
+            auto load_group = [&](int j0, double (&dst)[MG][NV], double (&w)[MG][NG]) {
 #pragma unroll
                 for (int m = 0; m < MG; ++m) {
                     const int j = j0 + m < N0 ? j0 + m : N0 - 1;
                     const int o = base + C::st.off[j][0] + C::HX * (C::st.off[j][1] + C::HY * C::st.off[j][2]);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) u[m][v] = tile[v][o];
+                    for (int v = 0; v < NV; ++v) dst[m][v] = tile[v][o];
+#pragma unroll
+                    for (int p = 0; p < NG; ++p) w[m][p] = wk[j * NG + p];
                 }
+            };
+            auto pin_weights = [&](double (&w)[MG][NG]) {
+                if constexpr (!C::PIN_W) return;
+#pragma unroll
+                for (int m = 0; m < MG; ++m)
+#pragma unroll
+                    for (int p = 0; p < NG; ++p) asm volatile("" : "+s"(w[m][p]));
+            };
+            // (without room for two groups of weights in scalar registers the
+            // weight loads sit right before their FMAs and the wave waits there
+            // for everything in flight: the reads are then not issued ahead)
+            load_group(0, u[0], wb[0]);
+            pin_weights(wb[0]);
+#pragma unroll
+            for (int j0 = 0; j0 < N0; j0 += MG) {
+                const int cur = C::PIN_W ? (j0 / MG) & 1 : 0;
+                const bool more = j0 + MG < N0;
+                if (C::PIN_W && more) load_group(j0 + MG, u[cur ^ 1], wb[cur ^ 1]);
+                if (!C::PIN_W && j0 > 0) load_group(j0, u[0], wb[0]);
 #pragma unroll
                 for (int m = 0; m < MG; ++m) {
                     if (j0 + m >= N0) break;
 #pragma unroll
-                    for (int p = 0; p < NG; ++p) {
-                        const double w = wk[(j0 + m) * NG + p];
+                    for (int p = 0; p < NG; ++p)
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) acc[p][v] = fma(w, u[m][v], acc[p][v]);
-                    }
+                        for (int v = 0; v < NV; ++v) acc[p][v] = fma(wb[cur][m][p], u[cur][m][v], acc[p][v]);
                 }
 #pragma unroll
                 for (int p = 0; p < NG; ++p) {
@@ -133,17 +196,18 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
                         asm volatile("" : "+v"(acc[p][0]), "+v"(acc[p][1]), "+v"(acc[p][2]), "+v"(acc[p][3]),
                                      "+v"(acc[p][4]));
                 }
+                if (C::PIN_W && more) pin_weights(wb[cur ^ 1]);
                 asm volatile("" : "+v"(base) : "v"(acc[NG - 1][NV - 1]));
             }
 #pragma unroll
             for (int p = 0; p < NG; ++p) {
                 double q = 0.0;
-                bad = bad || !point_entropy<D>(acc[p], gam, q);
+                bad = bad || !scaled_entropy<D>(acc[p], gam, irho_ref, ser, q);
                 if (side == 0) q0[p] = q;
                 else jmax = fmax(jmax, fabs(q - q0[p]));
             }
         }
-        J[(long)a * g.ncell + cell] = bad ? INFINITY : jmax;
+        J[(long)a * g.ncell + cell] = bad || !(rho_ref > 0.0) ? INFINITY : jmax * qscale;
     }
 }
 
@@ -178,9 +242,13 @@ hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *U, double *
                       hipStream_t s)
 {
     using C = KxCfg<D, R>;
+    KxSeries ser;
+    for (int k = 1; k <= KX_SERIES_K; ++k) ser.a[k - 1] = (1.0 - k - g.gamma) / k;
+    ser.xmax = g.gamma <= 10.0 ? 1.0 / 32 : -1.0;
     const long nblk = (long)((g.n[0] + C::TX - 1) / C::TX) * ((g.n[1] + C::TY - 1) / C::TY) *
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
-    hipLaunchKernelGGL((k_kxrcf_jump<D, R>), dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(C::NT), 0, s, U, kw, J, g);
+    hipLaunchKernelGGL((k_kxrcf_jump<D, R>), dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(C::NT), 0, s, U, kw, J, g,
+                       ser);
     if (flags)
         hipLaunchKernelGGL((k_kxrcf_flags<D>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, U, J, flags,
                            g, thr);
