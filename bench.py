@@ -6,11 +6,14 @@ reconstruction, face-flux and update kernels) over the whole grid of the
 workload, with the state already resident in HBM.  The metric is cell-updates
 per second per Runge-Kutta stage: cells * 3 * steps / elapsed.
 
-Prints one JSON line.  `roofline` covers the dominant kernel (reconstruction):
-its algorithmic FP64 flops per launch over its average launch time, measured
-with HIP events on the library's stream over the timed steps.  `cpu_baseline`
-times the FP64 CPU oracle on a bounded periodic sub-box of the same initial
-state (rank 0, N = 1).
+Prints one JSON line.  The headline `value` is the split-precision path with
+the learned gate; the plain FP64 path, the ungated split path and the FP64 path
+driven by the paper's KXRCF indicator (the two-pass reconstruction) are timed
+beside it on the same state and step.  `roofline` covers the dominant kernel of
+each: algorithmic bytes (or FP64 flops) per launch over its average launch time,
+measured with HIP events on the library's stream over the timed steps.
+`cpu_baseline` times the FP64 CPU oracle on a bounded periodic sub-box of the
+same initial state (rank 0, N = 1).
 """
 from __future__ import annotations
 
@@ -61,6 +64,7 @@ def mixed_bytes_per_cell(d: int, R: int, gated: bool) -> int:
 _KERNEL_SOURCES = {
     "k_recon_mixed": ["rhs_mixed.hip", "device_common.hpp", "stencil.hpp", "kernels.hpp"],
     "k_recon": ["rhs_fp64.hip", "device_common.hpp", "stencil.hpp", "kernels.hpp"],
+    "k_kxrcf_jump": ["kxrcf.hip", "device_common.hpp", "stencil.hpp", "kernels.hpp"],
 }
 
 
@@ -119,13 +123,23 @@ def cpu_baseline(U_host, cfg, budget_s: float):
                       f"{t:.2f} s"}
 
 
-def _time_path(dev, U0, dt, steps, warmup, mode, kfvm, torch, gate=None):
+def kxrcf_flops_per_cell(d: int, R: int) -> int:
+    """Algorithmic FP64 flops of the KXRCF jump kernel per cell (FMA = 2): per axis
+    the unlimited states of both sides of the upper face at its Gauss points, one
+    dot product of length |S0| per (side, point, variable).  The entropies (a few
+    dozen flops per point) are not counted."""
+    _, npts, _, _, n0 = _SHAPES[(d, R)]
+    return 2 * npts * (d + 2) * n0        # 2 D sides x points per face = n_pts dot products per variable
+
+
+def _time_path(dev, U0, dt, steps, warmup, mode, kfvm, torch, gate=None, indicator=None):
     """Warm up on a scratch copy, then time `steps` SSP-RK3 steps from U0."""
     dev.set_precision(mode)
     if gate is None:
         dev.set_gate(None)
     else:
         dev.set_gate(torch.from_numpy(gate[0]).cuda(), gate[1])
+    dev.set_indicator(indicator)
     Uw = U0.clone()
     for _ in range(warmup):
         dev.step(Uw, dt)
@@ -185,6 +199,12 @@ def main():
 
     U_plain, t_plain, kt_plain = _time_path(dev, U0, dt, args.steps, args.warmup, "fp64", kfvm, torch)
     print(f"# plain fp64: {t_plain / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    U_kx, t_kx, kt_kx = _time_path(dev, U0, dt, args.steps, args.warmup, "fp64", kfvm, torch, indicator="kxrcf")
+    kx_flagged = float(dev.get_flags().float().mean())
+    print(f"# fp64 + KXRCF two-pass: {t_kx / args.steps * 1e3:.2f} ms/step, flagged {kx_flagged:.4f}",
+          file=sys.stderr, flush=True)
+    l1_kx = float((U_kx[0] - U_plain[0]).abs().mean())
+    del U_kx
     U_ung, t_ung, kt_ung = _time_path(dev, U0, dt, args.steps, args.warmup, args.mixed, kfvm, torch)
     print(f"# {args.mixed}: {t_ung / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
     l1_ung = float((U_ung[0] - U_plain[0]).abs().mean())
@@ -206,6 +226,15 @@ def main():
                 "traffic": profiled_traffic("k_recon", args.workload),
                 "flops_per_cell": recon_flops_per_cell(d, R), "alg_bytes_per_cell": recon_bytes_per_cell(d, R),
                 "hbm_gbs_alg": recon_bytes_per_cell(d, R) * ncell / avg / 1e9, "avg_launch_ms": avg * 1e3}
+
+    def kx_roof(kt):
+        ms, nl = kt["indicator"]
+        avg = ms / nl / 1e3
+        ach = kxrcf_flops_per_cell(d, R) * ncell / avg / 1e12
+        return {"kernel": "k_kxrcf_jump (+ k_kxrcf_flags)", "bound": "alu", "achieved": ach,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "traffic": profiled_traffic("k_kxrcf_jump", args.workload),
+                "flops_per_cell": kxrcf_flops_per_cell(d, R), "avg_launch_ms": avg * 1e3}
 
     per_launch = lambda kt: {k: (v[0] / v[1] if v[1] else None) for k, v in kt.items()}
     mix_ms, mix_n = kt_mix["recon"]
@@ -242,6 +271,10 @@ def main():
                        "dtype": "f64", "roofline": roof(kt_plain), "kernels_ms_per_launch": per_launch(kt_plain)},
         "mixed_ungated": {"value": ncell * stages / t_ung, "ms_per_step": t_ung / args.steps * 1e3,
                           "kernels_ms_per_launch": per_launch(kt_ung)},
+        "fp64_kxrcf": {"value": ncell * stages / t_kx, "ms_per_step": t_kx / args.steps * 1e3, "dtype": "f64",
+                       "indicator": "KXRCF two-pass, m = 3/2", "flagged_fraction": kx_flagged,
+                       "l1_rho_vs_fp64_weno_everywhere": l1_kx,
+                       "roofline": kx_roof(kt_kx), "kernels_ms_per_launch": per_launch(kt_kx)},
         "speedup_vs_plain_fp64": t_plain / t_mix,
     }
     if not args.no_cpu_baseline:
