@@ -378,6 +378,25 @@ static void kxrcf_rows(const double *tab, std::vector<double> &kw)
     using S = kfvm::Stencil<D, R>;
     constexpr int N0 = S::N0, NG = S::NG;
     kw.assign((size_t)kfvm::kxrcf_table_size(D, R), 0.0);
+    if constexpr (kfvm::kx_all_axes(D, R)) {
+        // [member][axis][point] upper-face rows over S0, then per member of the
+        // neighbours' union and per axis it belongs to, the n_g lower-face rows
+        using Un = kfvm::KxUnion<D, R>;
+        static constexpr Un un{};
+        for (int j = 0; j < N0; ++j)
+            for (int a = 0; a < D; ++a)
+                for (int p = 0; p < NG; ++p) kw[((size_t)j * D + a) * NG + p] = tab[((2 * a + 1) * NG + p) * N0 + j];
+        double *kn = kw.data() + (size_t)N0 * D * NG;
+        for (int m = 0; m < Un::NU; ++m) {
+            int k = un.woff[m];
+            for (int a = 0; a < D; ++a) {
+                if (un.j[m][a] < 0) continue;
+                for (int p = 0; p < NG; ++p) kn[k + p] = tab[((2 * a) * NG + p) * N0 + un.j[m][a]];
+                k += NG;
+            }
+        }
+        return;
+    }
     for (int a = 0; a < D; ++a)
         for (int side = 0; side < 2; ++side)
             for (int j = 0; j < N0; ++j)

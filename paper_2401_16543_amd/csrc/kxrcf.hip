@@ -84,6 +84,102 @@ __device__ __forceinline__ bool scaled_entropy(const double *u, double gam, doub
     return true;
 }
 
+// Pin every accumulator (empty asm): the FMAs that feed them are complete here.
+template <int NP, int NV>
+__device__ __forceinline__ void pin_acc(double (&acc)[NP][NV])
+{
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if constexpr (NV == 4)
+            asm volatile("" : "+v"(acc[p][0]), "+v"(acc[p][1]), "+v"(acc[p][2]), "+v"(acc[p][3]));
+        else
+            asm volatile("" : "+v"(acc[p][0]), "+v"(acc[p][1]), "+v"(acc[p][2]), "+v"(acc[p][3]), "+v"(acc[p][4]));
+    }
+}
+
+// The upper-face jumps of every axis (infinity where a state is not admissible)
+// in two passes over LDS: the cell's own
+// upper-face rows of all axes over S0 (each average read feeds d n_g points),
+// then the upper neighbours' lower-face rows over the union of their stencils
+// (an average shared by several neighbours' stencils is read once).  Weights:
+// [member][axis][point] for the first pass, then the union's layout.
+template <int D, int R>
+__device__ __forceinline__ void jumps_all_axes(const double (*tile)[KxCfg<D, R>::HN], int lc,
+                                               const double *__restrict__ kw, double gam, double irho_ref,
+                                               const KxSeries &ser, double (&jump)[D])
+{
+    using C = KxCfg<D, R>;
+    using Un = KxUnion<D, R>;
+    constexpr int NV = C::NV, NG = C::NG, N0 = C::N0, NP = D * NG;
+    constexpr Un un{};
+    double acc[NP][NV], q0[NP];
+    bool bad[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) bad[a] = false;
+    int base = lc;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[p][v] = 0.0;
+    // the next member's LDS index depends on the pinned accumulators, so one
+    // member's reads are in flight at a time (not all of them hoisted up front)
+#pragma unroll
+    for (int j = 0; j < N0; ++j) {
+        const int o = base + C::st.off[j][0] + C::HX * (C::st.off[j][1] + C::HY * C::st.off[j][2]);
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = tile[v][o];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double w = kw[j * NP + p];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[p][v] = fma(w, u[v], acc[p][v]);
+        }
+        pin_acc(acc);
+        asm volatile("" : "+v"(base) : "v"(acc[NP - 1][NV - 1]));
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        q0[p] = 0.0;
+        bad[p / NG] = bad[p / NG] || !scaled_entropy<D>(acc[p], gam, irho_ref, ser, q0[p]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[p][v] = 0.0;
+    }
+    const double *kn = kw + N0 * NP;
+#pragma unroll
+    for (int m = 0; m < Un::NU; ++m) {
+        const int o = base + un.off[m][0] + C::HX * (un.off[m][1] + C::HY * un.off[m][2]);
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = tile[v][o];
+        int k = un.woff[m];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (un.j[m][a] < 0) continue;
+#pragma unroll
+            for (int p = 0; p < NG; ++p) {
+                const double w = kn[k + p];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[a * NG + p][v] = fma(w, u[v], acc[a * NG + p][v]);
+            }
+            k += NG;
+        }
+        pin_acc(acc);
+        asm volatile("" : "+v"(base) : "v"(acc[NP - 1][NV - 1]));
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double jm = 0.0;
+#pragma unroll
+        for (int p = 0; p < NG; ++p) {
+            double q = 0.0;
+            bad[a] = bad[a] || !scaled_entropy<D>(acc[a * NG + p], gam, irho_ref, ser, q);
+            jm = fmax(jm, fabs(q - q0[a * NG + p]));
+        }
+        jump[a] = bad[a] ? INFINITY : jm;
+    }
+}
+
 template <int D, int R>
 __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *__restrict__ U,
                                                                 const double *__restrict__ kw,
@@ -126,6 +222,14 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
     const double rho_ref = tile[0][lc], irho_ref = rcp64(rho_ref);
     const double qscale = rho_ref > 0.0 ? pow(rho_ref, -gam) : 0.0;
 
+    if constexpr (kx_all_axes(D, R)) {
+        double jump[D];
+        jumps_all_axes<D, R>(tile, lc, kw, gam, irho_ref, ser, jump);
+#pragma unroll
+        for (int a = 0; a < D; ++a) J[(long)a * g.ncell + cell] = !(rho_ref > 0.0) ? INFINITY : jump[a] * qscale;
+        return;
+    }
+    // 3D order 7 (nine points per face): one axis and one side at a time
 #pragma unroll 1
     for (int a = 0; a < D; ++a) {
         const int step = a == 0 ? 1 : (a == 1 ? C::HX : C::HX * C::HY);

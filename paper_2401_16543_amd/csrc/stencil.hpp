@@ -168,6 +168,67 @@ struct ChunkLayout {
     }
 };
 
+// Members of the KXRCF indicator's neighbour pass: the union over the axes a of
+// S0 + e_a (the stencils of the upper neighbours), in lexicographic order of the
+// offset with x slowest; per member the S0 index of (offset - e_a) for each axis
+// (-1 outside S0) and where its weights start in the pass's table, which holds
+// for each member, for each axis it belongs to, the n_g lower-face rows.
+template <int D, int R>
+struct KxUnion {
+    using S = Stencil<D, R>;
+    static constexpr int count()
+    {
+        constexpr S st{};
+        int c = 0;
+        for (int i = -R; i <= R + 1; ++i)
+            for (int j = -R; j <= R + 1; ++j)
+                for (int k = (D == 3 ? -R : 0); k <= (D == 3 ? R + 1 : 0); ++k) {
+                    bool in = false;
+                    for (int a = 0; a < D; ++a) {
+                        const int o[3] = {i - (a == 0), j - (a == 1), k - (a == 2)};
+                        for (int h = 0; h < S::N0; ++h)
+                            if (st.off[h][0] == o[0] && st.off[h][1] == o[1] && st.off[h][2] == o[2]) in = true;
+                    }
+                    if (in) ++c;
+                }
+        return c;
+    }
+    static constexpr int NU = count();
+    int off[NU][3];
+    int j[NU][3];
+    int woff[NU + 1];
+    constexpr KxUnion() : off{}, j{}, woff{}
+    {
+        constexpr S st{};
+        int c = 0, w = 0;
+        for (int i = -R; i <= R + 1; ++i)
+            for (int jj = -R; jj <= R + 1; ++jj)
+                for (int k = (D == 3 ? -R : 0); k <= (D == 3 ? R + 1 : 0); ++k) {
+                    int idx[3] = {-1, -1, -1};
+                    bool in = false;
+                    for (int a = 0; a < D; ++a) {
+                        const int o[3] = {i - (a == 0), jj - (a == 1), k - (a == 2)};
+                        for (int h = 0; h < S::N0; ++h)
+                            if (st.off[h][0] == o[0] && st.off[h][1] == o[1] && st.off[h][2] == o[2]) idx[a] = h;
+                        in = in || idx[a] >= 0;
+                    }
+                    if (!in) continue;
+                    off[c][0] = i; off[c][1] = jj; off[c][2] = k;
+                    woff[c] = w;
+                    for (int a = 0; a < 3; ++a) {
+                        j[c][a] = idx[a];
+                        if (idx[a] >= 0) w += S::NG;
+                    }
+                    ++c;
+                }
+        woff[c] = w;
+    }
+};
+
+// The KXRCF first pass takes every axis at once where the accumulators of all
+// upper-face points fit (d n_g <= 12); 3D order 7 takes one axis and side at a time.
+constexpr bool kx_all_axes(int D, int R) { return D * ipow(R, D - 1) <= 12; }
+
 // linear weights of section 3.2 (gamma_hi = gamma_lo = 0.8)
 template <int D>
 constexpr double linear_weight(int q)
