@@ -42,6 +42,12 @@ typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int SB = 13;   // per-cell increment scale: max |delta| * 2^(SB - e) in [2^13, 2^14)
+// Least exponent e of that scale, so that 2^(SB - e) stays finite: increments
+// ahead of a wave front decay to float64 denormals (seen: 6e-314), whose scale
+// would overflow.  Below 2^e_min the increments are scaled by less than the
+// nominal factor; they are far under float32's range anyway.
+constexpr int E_MIN_D = -1000;      // float64 scaling
+constexpr int E_MIN_F = SB - 127;   // float32 scaling (2^127 is the largest finite power)
 constexpr double FLAT_REL = 0x1p-40;   // gate: increments below this fraction of the scale are flat
 
 // 3D tiles are 8 x 8 x 8 here (8 x 8 x 4 for R = 3): the threads of a block
@@ -297,7 +303,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
     amax = pair_max(amax);
     int ex = 0;
     if (amax > 0.0) frexp(amax, &ex);          // amax in [2^(ex-1), 2^ex)
-    const int e = ex - 1;
+    const int e = max(ex - 1, E_MIN_D);
     const double sc = ldexp(1.0, SB - e);
     const int ue = e - SB - sw;                    // accumulator units: value = acc * 2^ue
     // scaled increments in float32 (kept as such: otherwise the two roundings
@@ -352,7 +358,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
             gmax = pair_max(gmax);
             int gex = 0;
             if (gmax > 0.0) frexp(gmax, &gex);
-            const double gs = ldexp(1.0, -gex);
+            const double gs = ldexp(1.0, -max(gex, E_MIN_D));
 #pragma unroll
             for (int ks = 0; ks < KSG; ++ks) {
                 float gx[8];
@@ -711,7 +717,7 @@ __device__ __forceinline__ int gate_bit(const double (*tile)[MCfg<D, 2>::HN], in
     amax = pair_max(amax);
     int ex = 0;
     if (amax > 0.0) frexp(amax, &ex);
-    const double sc = ldexp(1.0, SB + 1 - ex);
+    const double sc = ldexp(1.0, SB + 1 - max(ex, E_MIN_D + 1));
     uint4 xb[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -845,7 +851,7 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
     amax = pair_max(amax);
     int ex = 0;
     if (amax > 0.f) frexpf(amax, &ex);         // amax in [2^(ex-1), 2^ex)
-    const int e = ex - 1;
+    const int e = max(ex - 1, E_MIN_F);
     const int ue = e - SB - sw;                  // accumulator units: value = acc * 2^ue
     uint4 bh[KS], bl[KS];
 #pragma unroll

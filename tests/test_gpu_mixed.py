@@ -207,3 +207,38 @@ def test_mixed_hll(K, oracle_mod):
     e = rel_err(dev.rhs(U.cuda()).cpu().numpy(), orc.rhs(U.numpy()))
     say(f"  rhs rel err {e:.3e}")
     assert e <= 2e-5
+
+
+@pytest.mark.parametrize("d,R,mode,gated", [(2, 2, "split_f16", False), (2, 2, "split_f16", True),
+                                              (3, 2, "split_f16", False), (3, 2, "split_bf16", True),
+                                              (3, 3, "split_f16", False), (3, 3, "split_f16", True)])
+def test_mixed_tiny_increments_stay_finite(K, oracle_mod, d, R, mode, gated):
+    """Ahead of a wave front the increments of a quiescent state decay to float64
+    denormals (seen on the tilted Sod tube: 6e-314 in the momentum).  The per-cell
+    scale 2^(SB - e) must stay finite there: a uniform state at rest with
+    momentum perturbations of 1e-36 (below float32's normal range) and 6e-314 in a
+    few cells gives a finite RHS equal to the FP64 one to the path's tolerance."""
+    from paper_2401_16543_amd import gate
+    say(f"case tiny increments d={d} R={R} {mode} gated={gated}")
+    n = (16,) * d
+    U = np.zeros((d + 2,) + n)
+    U[0] = 0.125
+    U[d + 1] = 0.25
+    idx = tuple(slice(3, 6) for _ in range(d))
+    U[(1,) + idx] = 6e-314
+    U[(d,) + tuple(slice(9, 12) for _ in range(d))] = -1e-36
+    U = torch.from_numpy(U)
+    ref = oracle_mod.Oracle(d, R, n).rhs(U.numpy())
+    dev = K.KFVM(d, n, order=2 * R + 1)
+    dev.set_precision(mode)
+    dev.set_checking(True)
+    if gated:
+        params, thr, _ = gate.load(d)
+        dev.set_gate(torch.from_numpy(params).cuda(), thr)
+    got = dev.rhs(U.cuda()).cpu().numpy()
+    assert np.isfinite(got).all()
+    # the RHS is at rounding level of the state (1e-16 x 0.25 / dx), the tiny
+    # momenta below it: compare absolutely
+    err = np.abs(got - ref).max()
+    say(f"  max |rhs - oracle| {err:.3e}")
+    assert err <= 1e-12
