@@ -228,3 +228,51 @@ WORKLOADS = {
     "3d_jumps_384_r3": dict(d=3, n=384, R=3, gamma=1.4, cfl=0.4, steps=30,
                             spec=lambda: discontinuous(5, 3, 4, 10.0, 50.0, M=16)),
 }
+
+
+# ----------------------------------------------------------------- Sod tube ---
+SOD_GAMMA = 1.4
+SOD_LEFT = (1.0, 1.0)        # (rho, p), at rest
+SOD_RIGHT = (0.125, 0.1)
+
+
+def sod_parallel_coordinate(config: str, x, y):
+    """The coordinate along which the Sod solution varies: x itself (aligned) or
+    x_par = (2x + y) / sqrt 5 (tilted, tan theta = 1/2)."""
+    return x if config == "aligned" else (2.0 * x + y) / math.sqrt(5.0)
+
+
+def sod(config: str, R: int, device="cpu"):
+    """Cell averages of the Sod shock tube on a periodic grid, by the tensor
+    Gauss-Legendre rule with R points per axis (the rule of the paper's initial
+    conditions).  Left state (rho, p) = (1, 1), right (0.125, 0.1), at rest,
+    gamma = 1.4; the left state fills the coordinate s in [-1/2, 1/2] modulo 2.
+
+    "aligned": [0, 2) x [0, 0.08), spacing 1/100 (200 x 8 cells): the grid-aligned
+    tube on [0, 1] and its mirror image on [1, 2), which stand in for the
+    outflow boundaries until the waves of the two interfaces meet (after
+    t = 0.2); s = x.  "tilted": [0, sqrt 5) x [0, 2 sqrt 5), spacing sqrt(5)/250
+    (250 x 500 cells), s = (2x + y) / sqrt 5.
+
+    Returns (U [4, ny, nx] float64 tensor, dict(n=(nx, ny), dx))."""
+    if config == "aligned":
+        nx, ny, h = 200, 8, 0.01
+    elif config == "tilted":
+        nx, ny, h = 250, 500, math.sqrt(5.0) / 250
+    else:
+        raise ValueError(config)
+    g, w = np.polynomial.legendre.leggauss(R)
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    Y, X = np.meshgrid(yc, xc, indexing="ij")
+    rho = np.zeros((ny, nx))
+    p = np.zeros((ny, nx))
+    for gy, wy in zip(g, w):
+        for gx, wx in zip(g, w):
+            s = sod_parallel_coordinate(config, X + 0.5 * gx * h, Y + 0.5 * gy * h)
+            left = np.abs(np.mod(s + 0.5, 2.0) - 0.5) <= 0.5
+            ww = 0.25 * wx * wy
+            rho += ww * np.where(left, SOD_LEFT[0], SOD_RIGHT[0])
+            p += ww * np.where(left, SOD_LEFT[1], SOD_RIGHT[1])
+    U = np.stack([rho, np.zeros_like(rho), np.zeros_like(rho), p / (SOD_GAMMA - 1.0)])
+    return torch.from_numpy(U).to(device), {"n": (nx, ny), "dx": h}

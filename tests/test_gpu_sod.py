@@ -1,0 +1,67 @@
+"""The Sod shock tube (section 6.2) on the GPU against its exact solution, in
+the paper's two configurations: grid-aligned (the tube and its mirror image on a
+periodic domain, which stand in for the outflow boundaries until t = 0.2) and
+tilted by tan theta = 1/2 on the periodic domain [0, sqrt 5) x [0, 2 sqrt 5).
+Density L1 error over the cells of the tube at t = 0.2, SSP-RK3 at CFL 0.4
+(the paper uses its adaptive SSP(4,3,2); the figure it shows has no numbers)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_16543_amd import inputs
+
+import exact_riemann as ER
+
+pytestmark = pytest.mark.gpu
+T = 0.2
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2401_16543_amd import kfvm
+    kfvm.load_library()
+    return kfvm
+
+
+def _run(K, config, R, path):
+    from paper_2401_16543_amd import gate
+    U, m = inputs.sod(config, R, device="cuda")
+    U = U.contiguous()
+    dev = K.KFVM(2, m["n"], dx=[m["dx"]] * 2, order=2 * R + 1, gamma=inputs.SOD_GAMMA)
+    dev.set_checking(True)
+    if path.startswith("split"):
+        dev.set_precision("split_f16")
+    if path == "fp64_kxrcf":
+        dev.set_indicator("kxrcf", 1.5)
+    if path == "split_gate":
+        params, thr, _ = gate.load(2)
+        dev.set_gate(torch.from_numpy(params).cuda(), thr)
+    t, steps = 0.0, 0
+    while t < T - 1e-14:
+        dt = min(dev.cfl_dt(U, 0.4), T - t)
+        dev.step(U, dt)
+        t += dt
+        steps += 1
+    rho = U[0].cpu().numpy()
+    l1, mx = ER.sod_l1_error(rho, config, m["n"], m["dx"], T)
+    return l1, mx, steps, U
+
+
+@pytest.mark.parametrize("R", [2, 3])
+@pytest.mark.parametrize("path", ["fp64", "fp64_kxrcf", "split_f16", "split_gate"])
+def test_sod_matches_exact_solution(K, R, path):
+    res = {}
+    for config in ("aligned", "tilted"):
+        say(f"case sod {config} R={R} {path}")
+        l1, mx, steps, U = _run(K, config, R, path)
+        say(f"  {steps} steps: L1 rho error {l1:.3e}, max {mx:.3f}")
+        res[config] = l1
+        assert np.isfinite(U.cpu().numpy()).all()
+        # measured 2.8e-3 .. 4.0e-3 on every path: discontinuities spread over a few cells
+        assert l1 <= 5e-3 and mx <= 0.07
+    # the scheme has little preference for grid-aligned features (section 6.2)
+    assert res["tilted"] <= 1.25 * res["aligned"]
