@@ -45,7 +45,10 @@ class _Ctx(C.Structure):
         ("gl_w", C.POINTER(C.c_double)), ("eps", C.c_double),
         ("limiter", C.c_int), ("kappa", C.c_double), ("riemann", C.c_int),
         ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)), ("kxrcf_m", C.c_double),
+        ("bc", C.c_int * 6), ("bc_state", C.c_double * 30),
     ]
+
+BC_KINDS = {"periodic": 0, "outflow": 1, "reflecting": 2, "inflow": 3}
 
 
 _lib = None
@@ -152,6 +155,21 @@ class Oracle:
     def _call(self, rc):
         if rc != 0:
             raise OracleError(f"oracle returned {rc}")
+
+    def set_boundary(self, axis: int, lower: str, upper: str, lower_state=None, upper_state=None):
+        """Boundary conditions of one axis (section 5.3, steps 1 and 4): "periodic"
+        on both sides, or any of "outflow", "reflecting", "inflow" per side; an
+        inflow side takes its conserved state (nvar values)."""
+        if (lower == "periodic") != (upper == "periodic"):
+            raise ValueError("periodic must be set on both sides of an axis")
+        for side, (kind, state) in enumerate(((lower, lower_state), (upper, upper_state))):
+            self._ctx.bc[2 * axis + side] = BC_KINDS[kind]
+            if kind == "inflow":
+                st = np.asarray(state, dtype=np.float64)
+                if st.shape != (self.nvar,):
+                    raise ValueError("an inflow side needs its conserved state")
+                for v in range(self.nvar):
+                    self._ctx.bc_state[(2 * axis + side) * 5 + v] = float(st[v])
 
     def set_kxrcf(self, m):
         """The KXRCF indicator (section 3.5) with threshold Delta^m picks the WENO

@@ -70,7 +70,11 @@ typedef struct {
     int weno;              /* 1: WENO-AO; 0: linear S0 reconstruction only */
     const uint8_t *flags;  /* optional [nvar][cells]: 1 = WENO, 0 = linear (gate replay) */
     double kxrcf_m;        /* > 0: the KXRCF indicator with threshold Delta^m picks the WENO cells */
+    int bc[3][2];          /* boundary condition per axis and side (lower, upper): BC_* below */
+    double bc_state[3][2][MAXV];   /* conserved inflow state per axis and side */
 } oracle_ctx;
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTING = 2, BC_INFLOW = 3 };
 
 /* ---------------------------------------------------------------- grid --- */
 static long ncells(const oracle_ctx *c) { return (long)c->n[0] * c->n[1] * c->n[2]; }
@@ -90,6 +94,71 @@ static void load_cell(const oracle_ctx *c, const double *U, long cell, double *u
 {
     long N = ncells(c);
     for (int v = 0; v < c->nvar; ++v) u[v] = U[v * N + cell];
+}
+
+/* ------------------------------------------------- boundary conditions --- */
+/* The average of the cell at offset off from `cell`, through the boundary
+ * conditions (the ghost fill of section 5.3, step 1).  Along a periodic axis the
+ * index wraps.  Past a non-periodic boundary the ghost cell is the nearest
+ * interior cell (outflow: zero-order extrapolation), the mirror-image cell
+ * (reflecting) or the given state (inflow).  When several axes leave the grid
+ * (a corner ghost), the first inflow axis in x, y, z order gives the state,
+ * otherwise every axis clamps or mirrors its index; the normal momentum of
+ * every reflecting axis is then negated. */
+static void neighbor_state(const oracle_ctx *c, const double *U, long cell, const int *off, double *u)
+{
+    long idx[3] = {cell % c->n[0], (cell / c->n[0]) % c->n[1], cell / ((long)c->n[0] * c->n[1])};
+    int flip[3] = {0, 0, 0}, fixed = -1;
+    for (int a = 0; a < c->dim; ++a) {
+        long g = idx[a] + off[a], n = c->n[a];
+        if (g >= 0 && g < n) {
+            idx[a] = g;
+            continue;
+        }
+        int side = g < 0 ? 0 : 1, kind = c->bc[a][side];
+        if (kind == BC_PERIODIC) {
+            idx[a] = ((g % n) + n) % n;
+        } else if (kind == BC_OUTFLOW) {
+            idx[a] = side ? n - 1 : 0;
+        } else if (kind == BC_REFLECTING) {
+            idx[a] = side ? 2 * n - 1 - g : -1 - g;
+            flip[a] = 1;
+        } else {
+            if (fixed < 0) fixed = 2 * a + side;
+            idx[a] = side ? n - 1 : 0;
+        }
+    }
+    if (fixed >= 0)
+        for (int v = 0; v < c->nvar; ++v) u[v] = c->bc_state[fixed / 2][fixed % 2][v];
+    else
+        load_cell(c, U, idx[0] + c->n[0] * (idx[1] + (long)c->n[1] * idx[2]), u);
+    for (int a = 0; a < c->dim; ++a)
+        if (flip[a]) u[1 + a] = -u[1 + a];
+}
+
+/* Does the face of `cell` on this side of axis a lie on a non-periodic boundary? */
+static int on_boundary(const oracle_ctx *c, long cell, int a, int side)
+{
+    if (c->bc[a][side] == BC_PERIODIC) return 0;
+    long i = a == 0 ? cell % c->n[0] : (a == 1 ? (cell / c->n[0]) % c->n[1] : cell / ((long)c->n[0] * c->n[1]));
+    return side ? i == c->n[a] - 1 : i == 0;
+}
+
+/* Riemann states outside the domain (section 5.3, step 4): at the Gauss points of
+ * the boundary face on this side of axis a, the outer state from the inner one
+ * (outflow: the same; reflecting: normal momentum negated; inflow: the given
+ * state), written where face_flux reads the outer cell's states: the upper face
+ * rows of a ghost below (side 0), the lower face rows of a ghost above (side 1). */
+static void ghost_face_states(const oracle_ctx *c, int a, int side, const double *own, double *ghost)
+{
+    int nv = c->nvar, ng = c->n_pts / (2 * c->dim);
+    for (int g = 0; g < ng; ++g) {
+        const double *in = own + ((2 * a + side) * ng + g) * nv;
+        double *out = ghost + ((2 * a + 1 - side) * ng + g) * nv;
+        int kind = c->bc[a][side];
+        for (int v = 0; v < nv; ++v) out[v] = kind == BC_INFLOW ? c->bc_state[a][side][v] : in[v];
+        if (kind == BC_REFLECTING) out[1 + a] = -out[1 + a];
+    }
 }
 
 /* ----------------------------------------------------------------- EOS --- */
@@ -175,7 +244,7 @@ static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, doubl
     double *W = (double *)malloc(sizeof(double) * n0 * nv);
     for (int h = 0; h < n0; ++h) {
         double uh[MAXV];
-        load_cell(c, U, wrap_index(c, cell, c->s0 + h * c->dim), uh);
+        neighbor_state(c, U, cell, c->s0 + h * c->dim, uh);
         matvec(nv, Phi, uh, W + h * nv);
     }
 
@@ -243,7 +312,7 @@ static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, doubl
             for (int dx = lo[0]; dx <= hi[0]; ++dx) {
                 int off[3] = {dx, dy, dz};
                 double un[MAXV];
-                load_cell(c, U, wrap_index(c, cell, off), un);
+                neighbor_state(c, U, cell, off, un);
                 if (!admissible(c, un)) return ERR_NONPHYSICAL;
                 double pn = pressure(c, un);
                 if (un[0] > rmax) rmax = un[0];
@@ -389,7 +458,7 @@ static void unlimited_states(const oracle_ctx *c, const double *U, long cell, do
     for (int i = 0; i < np * nv; ++i) states[i] = 0.0;
     for (int j = 0; j < N0; ++j) {
         double u[MAXV];
-        load_cell(c, U, wrap_index(c, cell, c->s0 + mem[j] * c->dim), u);
+        neighbor_state(c, U, cell, c->s0 + mem[j] * c->dim, u);
         for (int s = 0; s < np; ++s)
             for (int v = 0; v < nv; ++v) states[s * nv + v] += tab[s * N0 + j] * u[v];
     }
@@ -437,7 +506,10 @@ static double kxrcf_measure(const oracle_ctx *c, const double *U, long cell, dou
         for (int side = 0; side < 2; ++side) {
             int off[3] = {0, 0, 0};
             off[a] = side ? 1 : -1;
-            unlimited_states(c, U, wrap_index(c, cell, off), nb);
+            if (on_boundary(c, cell, a, side))
+                ghost_face_states(c, a, side, own, nb);
+            else
+                unlimited_states(c, U, wrap_index(c, cell, off), nb);
             double j = side ? face_jump(c, own, nb, a) : face_jump(c, nb, own, a);
             if (jumps) jumps[2 * a + side] = j;
             if (!(j <= J)) J = j;
@@ -523,16 +595,28 @@ int oracle_rhs(const oracle_ctx *c, const double *U, double *dUdt)
 #pragma omp parallel for schedule(static)
     for (long cell = 0; cell < N; ++cell) {
         double acc[MAXV] = {0};
+        double *gh = (double *)malloc(sizeof(double) * np * nv);
+        const double *own = st + cell * np * nv;
         for (int a = 0; a < c->dim; ++a) {
             int up[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
             up[a] = 1; dn[a] = -1;
-            long cu = wrap_index(c, cell, up), cd = wrap_index(c, cell, dn);
             double Fp[MAXV], Fm[MAXV];
-            face_flux(c, st + cell * np * nv, st + cu * np * nv, a, Fp);
-            face_flux(c, st + cd * np * nv, st + cell * np * nv, a, Fm);
+            if (on_boundary(c, cell, a, 1)) {
+                ghost_face_states(c, a, 1, own, gh);
+                face_flux(c, own, gh, a, Fp);
+            } else {
+                face_flux(c, own, st + wrap_index(c, cell, up) * np * nv, a, Fp);
+            }
+            if (on_boundary(c, cell, a, 0)) {
+                ghost_face_states(c, a, 0, own, gh);
+                face_flux(c, gh, own, a, Fm);
+            } else {
+                face_flux(c, st + wrap_index(c, cell, dn) * np * nv, own, a, Fm);
+            }
             for (int v = 0; v < nv; ++v) acc[v] -= (Fp[v] - Fm[v]) / c->dx[a];
         }
         for (int v = 0; v < nv; ++v) dUdt[v * N + cell] = acc[v];
+        free(gh);
     }
     free(st);
     return OK;
@@ -560,7 +644,8 @@ int oracle_rhs_cells(const oracle_ctx *c, const double *U, long count, const lon
             long cell = cells[k / (2 * c->dim + 1)];
             int r = (int)(k % (2 * c->dim + 1)), off[3] = {0, 0, 0};
             if (r > 0) off[(r - 1) / 2] = (r - 1) % 2 ? 1 : -1;
-            target[k] = wrap_index(c, cell, off);
+            /* a neighbour past a non-periodic boundary is no cell: the sampled one stands in */
+            target[k] = r > 0 && on_boundary(c, cell, (r - 1) / 2, (r - 1) % 2) ? cell : wrap_index(c, cell, off);
             f[k] = kxrcf_flag(kxrcf_measure(c, U, target[k], NULL), thr);
         }
         for (long k = 0; k < nneed; ++k)
@@ -579,8 +664,14 @@ int oracle_rhs_cells(const oracle_ctx *c, const double *U, long count, const lon
         for (int a = 0; a < c->dim && e == OK; ++a) {
             int up[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
             up[a] = 1; dn[a] = -1;
-            e = cell_states(c, U, wrap_index(c, cell, up), st + np * nv);
-            if (e == OK) e = cell_states(c, U, wrap_index(c, cell, dn), st + 2 * np * nv);
+            if (on_boundary(c, cell, a, 1))
+                ghost_face_states(c, a, 1, st, st + np * nv);
+            else
+                e = cell_states(c, U, wrap_index(c, cell, up), st + np * nv);
+            if (e == OK && on_boundary(c, cell, a, 0))
+                ghost_face_states(c, a, 0, st, st + 2 * np * nv);
+            else if (e == OK)
+                e = cell_states(c, U, wrap_index(c, cell, dn), st + 2 * np * nv);
             if (e != OK) break;
             double Fp[MAXV], Fm[MAXV];
             face_flux(c, st, st + np * nv, a, Fp);
