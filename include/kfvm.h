@@ -7,6 +7,9 @@
  * kernel-based finite volume WENO-AO scheme of May & Lee (arXiv 2401.16543),
  * and advances it with the three-stage SSP Runge-Kutta method of Shu & Osher.
  *
+ * Boundaries are periodic unless kfvm_set_boundary says otherwise (outflow,
+ * reflecting, inflow; FP64 path).
+ *
  * The right-hand side follows the paper's section 5.3: per cell the linearised
  * primitive variables W = Phi U with Phi from the cell's own average (section
  * 3.4.2, eq. consToLPMat), point values and derivatives from precomputed kernel
@@ -52,6 +55,7 @@ enum {
 enum { KFVM_FP64 = 0, KFVM_SPLIT_F16 = 1, KFVM_SPLIT_BF16 = 2 };   /* kfvm_set_precision */
 enum { KFVM_HLLC = 0, KFVM_HLL = 1 };                              /* kfvm_set_riemann */
 enum { KFVM_IND_NONE = 0, KFVM_IND_KXRCF = 1 };                    /* kfvm_set_indicator */
+enum { KFVM_BC_PERIODIC = 0, KFVM_BC_OUTFLOW = 1, KFVM_BC_REFLECTING = 2, KFVM_BC_INFLOW = 3 }; /* kfvm_set_boundary */
 
 typedef struct kfvm_ctx kfvm_ctx;
 
@@ -129,8 +133,30 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
  * nonlinear-weight normalisation, the limiter, the Riemann solver and the
  * Runge-Kutta update stay in float64.  The split modes need fewer than 2^30
- * cells (KFVM_ERR_ARG otherwise). */
+ * cells and a periodic grid (KFVM_ERR_ARG otherwise). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
+
+/* Boundary conditions of one axis (section 5.3: ghost cells filled by them,
+ * step 1; Riemann states outside the domain from the inner ones, step 4).
+ * lower, upper: KFVM_BC_PERIODIC on both sides (the default), or per side
+ *  - KFVM_BC_OUTFLOW: ghost cells copy the nearest interior cell (zero-order
+ *    extrapolation); the outer Riemann state is the inner one;
+ *  - KFVM_BC_REFLECTING: ghost cells are the mirror images with the normal
+ *    momentum negated; so is the outer Riemann state;
+ *  - KFVM_BC_INFLOW: ghost cells and outer Riemann states take the given state,
+ *    lower_state / upper_state: host pointers to nvar conserved values (ignored
+ *    for other kinds; the library copies them).
+ * At a corner ghost cell the first inflow axis in x, y, z order gives the state,
+ * otherwise every axis clamps or mirrors its index; the normal momentum of every
+ * reflecting axis is then negated.  The KXRCF jump at a boundary face is taken
+ * against the outer state.  Non-periodic grids run on the FP64 path only
+ * (KFVM_ERR_ARG in a split mode; kfvm_set_precision refuses the split modes on
+ * them).  Errors: KFVM_ERR_ARG (axis, kind, periodic on one side only, missing
+ * inflow state), KFVM_ERR_NONPHYSICAL (an inflow state with rho <= 0 or p <= 0).
+ * The first non-periodic axis allocates dim * nvar * (largest boundary plane)
+ * float64 of boundary-face fluxes. */
+int kfvm_set_boundary(kfvm_ctx *ctx, int axis, int lower, int upper, const double *lower_state,
+                      const double *upper_state);
 
 /* Positivity limiter of section 4 with flattener eta = 0: enabled != 0 turns it
  * on; bounds are widened by the factor (1 +- kappa), 0 <= kappa < 1. */

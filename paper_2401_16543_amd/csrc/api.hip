@@ -2,6 +2,7 @@
 // workspace ownership and dispatch to the HIP kernels.  See include/kfvm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +50,7 @@ struct kfvm_ctx {
     double kx_m = 1.5;
     double *d_kx_w = nullptr;       // S0 face rows as [axis][side][member][Gauss point]
     double *d_kx_jump = nullptr;    // [dim][ncell] largest entropy jump on each upper face
+    double *d_kx_jlo = nullptr;     // [dim][plane] jumps on the lower faces of non-periodic boundaries
 };
 
 namespace {
@@ -268,6 +270,8 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     }
     c->geom.ncell = ncell;
     c->geom.gamma = gamma;
+    c->geom.periodic = 1;
+    for (int a = 0; a < 3; ++a) c->work.plane = std::max(c->work.plane, ncell / c->geom.n[a]);
 
     const int ntab = kfvm_weights_size(dim, R);
     std::vector<double> host(ntab);
@@ -439,7 +443,12 @@ static int run_kxrcf(kfvm_ctx *c, const double *U, double m, double *J, uint8_t 
 {
     kfvm::Timing tm = timing_of(c);
     if (tm.on) tm.record(tm.self, kfvm::KT_INDICATOR, c->stream, 1);
-    hipError_t e = kfvm::launch_kxrcf(c->dim, c->R, c->geom, c->d_kx_w, U, J, flags, kxrcf_threshold(c, m), c->stream);
+    if (!c->geom.periodic && !c->d_kx_jlo) {
+        const int rc = alloc(c, (void **)&c->d_kx_jlo, sizeof(double) * (size_t)c->dim * c->work.plane);
+        if (rc != KFVM_OK) return rc;
+    }
+    hipError_t e = kfvm::launch_kxrcf(c->dim, c->R, c->geom, c->d_kx_w, c->d_tables, U, J, c->d_kx_jlo, c->work.plane,
+                                      flags, kxrcf_threshold(c, m), c->stream);
     if (tm.on) tm.record(tm.self, kfvm::KT_INDICATOR, c->stream, 0);
     if (e != hipSuccess) return hip_fail(c, e, "launch");
     return KFVM_OK;
@@ -527,6 +536,7 @@ int kfvm_set_precision(kfvm_ctx *c, int mode)
     if (mode != KFVM_FP64) {
         if (!kfvm::mixed_supported(c->dim, c->R))
             return fail(c, KFVM_ERR_ARG, "split precision is not available for this dimension and order");
+        if (!c->geom.periodic) return fail(c, KFVM_ERR_ARG, "the split-precision path takes periodic grids only");
         const int rc = prepare_mixed(c, mode);
         if (rc != KFVM_OK) return rc;
     }
@@ -610,6 +620,46 @@ int kfvm_set_flags(kfvm_ctx *c, const uint8_t *flags)
         c->gate_on = 0;
         c->indicator = KFVM_IND_NONE;
     }
+    return KFVM_OK;
+}
+
+int kfvm_set_boundary(kfvm_ctx *c, int axis, int lower, int upper, const double *lower_state,
+                      const double *upper_state)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (axis < 0 || axis >= c->dim) return fail(c, KFVM_ERR_ARG, "axis out of range");
+    const int kinds[2] = {lower, upper};
+    const double *states[2] = {lower_state, upper_state};
+    for (int side = 0; side < 2; ++side)
+        if (kinds[side] < KFVM_BC_PERIODIC || kinds[side] > KFVM_BC_INFLOW)
+            return fail(c, KFVM_ERR_ARG, "unknown boundary condition");
+    if ((lower == KFVM_BC_PERIODIC) != (upper == KFVM_BC_PERIODIC))
+        return fail(c, KFVM_ERR_ARG, "periodic must be set on both sides of an axis");
+    if (lower != KFVM_BC_PERIODIC && c->precision != KFVM_FP64)
+        return fail(c, KFVM_ERR_ARG, "the split-precision path takes periodic grids only");
+    for (int side = 0; side < 2; ++side) {
+        if (kinds[side] != KFVM_BC_INFLOW) continue;
+        if (!states[side]) return fail(c, KFVM_ERR_ARG, "an inflow side needs its state");
+        const double *u = states[side];
+        double ke = 0.0;
+        for (int a = 0; a < c->dim; ++a) ke += u[1 + a] * u[1 + a];
+        bool fin = true;
+        for (int v = 0; v < c->nvar; ++v) fin = fin && std::isfinite(u[v]);
+        if (!fin || !(u[0] > 0.0) || !((c->geom.gamma - 1.0) * (u[c->dim + 1] - 0.5 * ke / u[0]) > 0.0))
+            return fail(c, KFVM_ERR_NONPHYSICAL, "inflow state with rho <= 0 or p <= 0");
+    }
+    if (lower != KFVM_BC_PERIODIC && !c->work.fbar_top) {
+        const int rc = alloc(c, (void **)&c->work.fbar_top, sizeof(double) * (size_t)c->dim * c->nvar * c->work.plane);
+        if (rc != KFVM_OK) return rc;
+    }
+    for (int side = 0; side < 2; ++side) {
+        c->geom.bc[axis][side] = kinds[side];
+        for (int v = 0; v < 5; ++v)
+            c->geom.bc_state[axis][side][v] = kinds[side] == KFVM_BC_INFLOW && v < c->nvar ? states[side][v] : 0.0;
+    }
+    int periodic = 1;
+    for (int a = 0; a < c->dim; ++a) periodic = periodic && c->geom.bc[a][0] == KFVM_BC_PERIODIC;
+    c->geom.periodic = periodic;
     return KFVM_OK;
 }
 

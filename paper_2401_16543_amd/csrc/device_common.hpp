@@ -67,6 +67,57 @@ __device__ __forceinline__ int wrap_any(int i, int n)
     return r < 0 ? r + n : r;
 }
 
+// Average of the cell at grid coordinates (x, y, z), which may lie outside the
+// grid, through the boundary conditions (the ghost fill of section 5.3, step 1):
+// along a periodic axis the index wraps; past a non-periodic boundary the ghost
+// is the nearest interior cell (outflow), the mirror image (reflecting) or the
+// given state (inflow).  At a corner ghost the first inflow axis in x, y, z
+// order gives the state, otherwise every axis clamps or mirrors; the normal
+// momentum of every reflecting axis is then negated.
+template <int D>
+__device__ __forceinline__ void ghost_load(const double *__restrict__ U, const Geom &g, int x, int y, int z,
+                                           double *u)
+{
+    int idx[3] = {x, y, z}, fixed = -1;
+    bool flip[3] = {false, false, false};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int i = idx[a], n = g.n[a];
+        if (i >= 0 && i < n) continue;
+        const int side = i < 0 ? 0 : 1, kind = g.bc[a][side];
+        if (kind == BC_PERIODIC) {
+            const int r = i % n;
+            idx[a] = r < 0 ? r + n : r;
+        } else if (kind == BC_REFLECTING) {
+            // (a tile's unused far corner can lie past the mirror image: clamp)
+            idx[a] = min(max(side ? 2 * n - 1 - i : -1 - i, 0), n - 1);
+            flip[a] = true;
+        } else {
+            idx[a] = side ? n - 1 : 0;
+            if (kind == BC_INFLOW && fixed < 0) fixed = 2 * a + side;
+        }
+    }
+    if (D == 2) idx[2] = 0;
+    const long cell = idx[0] + (long)g.n[0] * (idx[1] + (long)g.n[1] * idx[2]);
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) u[v] = fixed >= 0 ? g.bc_state[fixed / 2][fixed % 2][v] : U[v * g.ncell + cell];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (flip[a]) u[1 + a] = -u[1 + a];
+}
+
+// Riemann state outside the domain at a boundary face of axis a (section 5.3,
+// step 4) from the inner one: the same (outflow), normal momentum negated
+// (reflecting) or the given state (inflow).
+template <int D>
+__device__ __forceinline__ void boundary_state(const Geom &g, int a, int side, const double *in, double *out)
+{
+    const int kind = g.bc[a][side];
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) out[v] = kind == BC_INFLOW ? g.bc_state[a][side][v] : in[v];
+    if (kind == BC_REFLECTING) out[1 + a] = -in[1 + a];
+}
+
 // 1/x from the hardware estimate and two Newton-Raphson steps r <- r + r (1 - x r)
 // (each squares the relative error): within an ulp or so of the rounded
 // quotient, for positive normal x, at half the cost of an IEEE division.

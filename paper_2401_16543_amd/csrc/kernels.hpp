@@ -6,11 +6,17 @@
 
 namespace kfvm {
 
+// Boundary conditions per axis and side (section 5.3, steps 1 and 4).
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTING = 2, BC_INFLOW = 3 };
+
 struct Geom {
     int n[3];          // cells per axis (n[2] = 1 in 2D)
     long ncell;
     double dx[3];
     double gamma;
+    int periodic;               // every axis periodic: ghost cells are a plain index wrap
+    int bc[3][2];               // BC_* per axis and side (lower, upper)
+    double bc_state[3][2][5];   // conserved inflow state per axis and side
 };
 
 struct Limiter {
@@ -29,7 +35,15 @@ struct Work {
     uint32_t *counts;  // [2] limiter cells, WENO (cell, var) pairs
     const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
     float *inc32;      // [n_pts][nvar][ncell] blended increments w_s - W_c (split-precision path)
+    double *fbar_top;  // [dim][nvar][plane] fluxes through the upper boundary faces of non-periodic axes
+    long plane;        // largest boundary plane (cells), the stride of fbar_top
 };
+
+// index of a cell in the boundary plane of axis a: its other two coordinates, the lower axis fastest
+__host__ __device__ inline long plane_index(int a, int cx, int cy, int cz, const int *n)
+{
+    return a == 0 ? cy + (long)n[1] * cz : (a == 1 ? cx + (long)n[0] * cz : cx + (long)n[0] * cy);
+}
 
 // Matrix-core operands of the split-precision path, in the per-lane layout of
 // v_mfma_f32_32x32x16: [tile][k-step][hi, lo][lane] slots of 8 16-bit values.
@@ -91,9 +105,12 @@ hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, do
 // (flags != nullptr) flags[nvar][ncell] = 1 where eq. kxrcf fails for threshold thr.
 // kw: the S0 face-point rows laid out [axis][side][member][Gauss point], side 0
 // the upper face of the cell, side 1 the lower face of its upper neighbour.
+// Non-periodic grids: the jumps at boundary faces come from the outer states the
+// boundary conditions give (upper faces into J, lower faces into Jlo[dim][plane],
+// plane stride `plane`); w0: the FP64 tables (stencil 0 leads).
 int kxrcf_table_size(int dim, int R);
-hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags,
-                        double thr, hipStream_t s);
+hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *w0, const double *U, double *J,
+                        double *Jlo, long plane, uint8_t *flags, double thr, hipStream_t s);
 
 // gate network: training and sample export (mlp.hip)
 int mlp_n_in(int dim);

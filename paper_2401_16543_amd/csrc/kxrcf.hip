@@ -17,6 +17,9 @@
 //          rho is within 1/32 of rho_c (pow otherwise), and the face maximum is
 //          scaled by rho_c^-gamma once.  Reads of a member group are issued one
 //          group ahead of the FMAs that use them.
+//   boundary  (non-periodic grids) one thread per cell: at the faces on a
+//          non-periodic boundary, the jump between the cell's unlimited state
+//          and the outer state the boundary condition gives.
 //   flags  one thread per cell: the largest jump over its 2d faces against
 //          Delta^m times the entropy of its own average.  Every variable of a
 //          flagged cell takes WENO-AO in the reconstruction that follows, the
@@ -202,6 +205,15 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
     const bool near = g.n[0] >= C::TX + R + 1 && g.n[1] >= C::TY + R + 1 && (D == 2 || g.n[2] >= C::TZ + R + 1);
     for (int i = threadIdx.x; i < C::HN; i += C::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+        if (!g.periodic) {
+            // non-periodic axes: ghost cells by the boundary conditions (the
+            // jumps of boundary faces are redone by k_kxrcf_boundary)
+            double u[NV];
+            ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tile[v][i] = u[v];
+            continue;
+        }
         const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
         const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
         const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
@@ -315,8 +327,59 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
     }
 }
 
+// Jumps at the faces of non-periodic boundaries, between the cell's unlimited
+// state and the outer state the boundary condition gives (section 5.3, step 4):
+// upper faces overwrite J, lower faces go to Jlo.  One thread per cell; the
+// stencil is read through the ghost fill and the S0 rows of the FP64 tables.
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_kxrcf_boundary(const double *__restrict__ U, const double *__restrict__ w0,
+                                                      double *__restrict__ J, double *__restrict__ Jlo, long plane,
+                                                      Geom g)
+{
+    using S = Stencil<D, R>;
+    constexpr S st{};
+    constexpr int NV = D + 2, NG = S::NG, N0 = S::N0;
+    const long cell = (long)blockIdx.x * 256 + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const int c[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+#pragma unroll 1
+    for (int a = 0; a < D; ++a)
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            if (g.bc[a][side] == BC_PERIODIC || c[a] != (side ? g.n[a] - 1 : 0)) continue;
+            double jm = 0.0;
+            bool bad = false;
+#pragma unroll 1
+            for (int p = 0; p < NG; ++p) {
+                const double *row = w0 + ((2 * a + side) * NG + p) * N0;
+                double in[NV], out[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) in[v] = 0.0;
+                int cx = c[0];
+#pragma unroll
+                for (int j = 0; j < N0; ++j) {
+                    double u[NV];
+                    ghost_load<D>(U, g, cx + st.off[j][0], c[1] + st.off[j][1], c[2] + st.off[j][2], u);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) in[v] = fma(row[j], u[v], in[v]);
+                    // the next member's address depends on this one's sums (empty
+                    // asm): one member's loads in flight, not all N0 hoisted
+                    asm volatile("" : "+v"(cx) : "v"(in[NV - 1]));
+                }
+                boundary_state<D>(g, a, side, in, out);
+                double qi = 0.0, qo = 0.0;
+                bad = bad || !point_entropy<D>(in, g.gamma, qi) || !point_entropy<D>(out, g.gamma, qo);
+                jm = fmax(jm, fabs(qo - qi));
+            }
+            const double j = bad ? INFINITY : jm;
+            if (side) J[(long)a * g.ncell + cell] = j;
+            else Jlo[(long)a * plane + plane_index(a, c[0], c[1], c[2], g.n)] = j;
+        }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_kxrcf_flags(const double *__restrict__ U, const double *__restrict__ J,
+                                                   const double *__restrict__ Jlo, long plane,
                                                    uint8_t *__restrict__ flags, Geom g, double thr)
 {
     constexpr int NV = D + 2;
@@ -328,7 +391,10 @@ __global__ __launch_bounds__(256) void k_kxrcf_flags(const double *__restrict__ 
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const long lower = cell + (c[a] == 0 ? (long)(g.n[a] - 1) * stride[a] : -stride[a]);
-        jm = fmax(jm, fmax(J[(long)a * g.ncell + cell], J[(long)a * g.ncell + lower]));
+        const double jl = c[a] == 0 && g.bc[a][0] != BC_PERIODIC
+                              ? Jlo[(long)a * plane + plane_index(a, c[0], c[1], c[2], g.n)]
+                              : J[(long)a * g.ncell + lower];
+        jm = fmax(jm, fmax(J[(long)a * g.ncell + cell], jl));
     }
     double u[NV];
 #pragma unroll
@@ -342,8 +408,8 @@ __global__ __launch_bounds__(256) void k_kxrcf_flags(const double *__restrict__ 
 }
 
 template <int D, int R>
-hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags, double thr,
-                      hipStream_t s)
+hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *w0, const double *U, double *J, double *Jlo,
+                      long plane, uint8_t *flags, double thr, hipStream_t s)
 {
     using C = KxCfg<D, R>;
     KxSeries ser;
@@ -353,9 +419,11 @@ hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *U, double *
                       (D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1);
     hipLaunchKernelGGL((k_kxrcf_jump<D, R>), dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(C::NT), 0, s, U, kw, J, g,
                        ser);
+    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
+    if (!g.periodic)
+        hipLaunchKernelGGL((k_kxrcf_boundary<D, R>), dim3(nb), dim3(256), 0, s, U, w0, J, Jlo, plane, g);
     if (flags)
-        hipLaunchKernelGGL((k_kxrcf_flags<D>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, U, J, flags,
-                           g, thr);
+        hipLaunchKernelGGL((k_kxrcf_flags<D>), dim3(nb), dim3(256), 0, s, U, J, Jlo, plane, flags, g, thr);
     return hipGetLastError();
 }
 
@@ -370,13 +438,13 @@ int kxrcf_table_size(int dim, int R)
     return -1;
 }
 
-hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *U, double *J, uint8_t *flags,
-                        double thr, hipStream_t s)
+hipError_t launch_kxrcf(int dim, int R, const Geom &g, const double *kw, const double *w0, const double *U, double *J,
+                        double *Jlo, long plane, uint8_t *flags, double thr, hipStream_t s)
 {
-    if (dim == 2 && R == 2) return kxrcf_impl<2, 2>(g, kw, U, J, flags, thr, s);
-    if (dim == 2 && R == 3) return kxrcf_impl<2, 3>(g, kw, U, J, flags, thr, s);
-    if (dim == 3 && R == 2) return kxrcf_impl<3, 2>(g, kw, U, J, flags, thr, s);
-    if (dim == 3 && R == 3) return kxrcf_impl<3, 3>(g, kw, U, J, flags, thr, s);
+    if (dim == 2 && R == 2) return kxrcf_impl<2, 2>(g, kw, w0, U, J, Jlo, plane, flags, thr, s);
+    if (dim == 2 && R == 3) return kxrcf_impl<2, 3>(g, kw, w0, U, J, Jlo, plane, flags, thr, s);
+    if (dim == 3 && R == 2) return kxrcf_impl<3, 2>(g, kw, w0, U, J, Jlo, plane, flags, thr, s);
+    if (dim == 3 && R == 3) return kxrcf_impl<3, 3>(g, kw, w0, U, J, Jlo, plane, flags, thr, s);
     return hipErrorInvalidValue;
 }
 

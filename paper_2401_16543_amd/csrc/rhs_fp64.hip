@@ -303,6 +303,14 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
     for (int i = threadIdx.x; i < C::HN; i += C::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+        if (!g.periodic) {
+            // non-periodic axes: ghost cells by the boundary conditions
+            double u[NV];
+            ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tile[v][i] = u[v];
+            continue;
+        }
         const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
         const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
         const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
@@ -439,42 +447,89 @@ __device__ __forceinline__ void lower_face_flux(const double *__restrict__ U, co
     }
 }
 
+// Flux through the face of `cell` on this side of axis A when it lies on a
+// non-periodic boundary: the cell's limited state inside, the state the
+// boundary condition gives outside (section 5.3, step 4).
+template <int D, int R, int A>
+__device__ __forceinline__ void boundary_face_flux(const double *__restrict__ U, const double *__restrict__ face,
+                                                   const double *__restrict__ theta, const Geom &g, long cell,
+                                                   int side, int hll, double *Fbar)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NG = S::NG;
+    double ref[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ref[v] = U[v * g.ncell + cell];
+    const double tr = theta[cell], tp = theta[g.ncell + cell];
+    PhiInv<D> pi;
+    pi.init(ref, g.gamma);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
+#pragma unroll 1
+    for (int gi = 0; gi < NG; ++gi) {
+        double w[NV], in[NV], out[NV], F[NV];
+        const int s = (2 * A + side) * NG + gi;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = face[(s * NV + v) * g.ncell + cell];
+        limited_state<D>(ref, pi, w, tr, tp, in);
+        boundary_state<D>(g, A, side, in, out);
+        if (side) riemann<D, A>(in, out, g.gamma, hll, F);
+        else riemann<D, A>(out, in, g.gamma, hll, F);
+        const double wt = face_weight<D, R>(gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[v] += wt * F[v];
+    }
+}
+
+// The fluxes of axis A at `cell`: through its lower face into fbar and, on an
+// upper non-periodic boundary, through its upper face into fbar_top.
+template <int D, int R, int A>
+__device__ __forceinline__ bool axis_fluxes(const double *__restrict__ U, const double *__restrict__ face,
+                                            const double *__restrict__ theta, double *__restrict__ fbar,
+                                            double *__restrict__ fbar_top, long plane, const Geom &g, long cell,
+                                            const int *c, int hll)
+{
+    constexpr int NV = D + 2;
+    double F[NV];
+    bool ok = true;
+    if (!g.periodic && c[A] == 0 && g.bc[A][0] != BC_PERIODIC) {
+        boundary_face_flux<D, R, A>(U, face, theta, g, cell, 0, hll, F);
+    } else {
+        int lc[3] = {c[0], c[1], c[2]};
+        lc[A] = wrapi(c[A] - 1, g.n[A]);
+        const long lower = lc[0] + (long)g.n[0] * (lc[1] + (long)g.n[1] * lc[2]);
+        lower_face_flux<D, R, A>(U, face, theta, g, cell, lower, hll, F);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { fbar[(A * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    if (!g.periodic && c[A] == g.n[A] - 1 && g.bc[A][1] != BC_PERIODIC) {
+        boundary_face_flux<D, R, A>(U, face, theta, g, cell, 1, hll, F);
+        const long pi = plane_index(A, c[0], c[1], c[2], g.n);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar_top[(A * NV + v) * plane + pi] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    return ok;
+}
+
 template <int D, int R>
 __global__ __launch_bounds__(256) void k_flux(const double *__restrict__ U, const double *__restrict__ face,
                                               const double *__restrict__ theta, double *__restrict__ fbar,
-                                              int *__restrict__ err, Geom g, int hll)
+                                              double *__restrict__ fbar_top, long plane, int *__restrict__ err,
+                                              Geom g, int hll)
 {
-    constexpr int NV = D + 2;
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
-    const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
-    const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
-    double F[NV];
-    bool ok = true;
-    {
-        const long lower = wrapi(cx - 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
-        lower_face_flux<D, R, 0>(U, face, theta, g, cell, lower, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(0 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
-    {
-        const long lower = cx + (long)g.n[0] * (wrapi(cy - 1, g.n[1]) + (long)g.n[1] * cz);
-        lower_face_flux<D, R, 1>(U, face, theta, g, cell, lower, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(1 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
-    if constexpr (D == 3) {
-        const long lower = cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz - 1, g.n[2]));
-        lower_face_flux<D, R, 2>(U, face, theta, g, cell, lower, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fbar[(2 * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
+    const int c[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+    bool ok = axis_fluxes<D, R, 0>(U, face, theta, fbar, fbar_top, plane, g, cell, c, hll);
+    ok = axis_fluxes<D, R, 1>(U, face, theta, fbar, fbar_top, plane, g, cell, c, hll) && ok;
+    if constexpr (D == 3) ok = axis_fluxes<D, R, 2>(U, face, theta, fbar, fbar_top, plane, g, cell, c, hll) && ok;
     if (!ok) *err = ERR_NONPHYSICAL;
 }
 
 // ----------------------------------------------------------------- update ---
 template <int D>
-__global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar, const double *__restrict__ U0,
+__global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar, const double *__restrict__ fbar_top,
+                                                long plane, const double *__restrict__ U0,
                                                 const double *__restrict__ Uin, double *__restrict__ out, Geom g,
                                                 int stage, double dt)
 {
@@ -483,16 +538,25 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar,
     if (cell >= g.ncell) return;
     const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
     const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
+    const int c[3] = {cx, cy, cz};
     long up[3];
     up[0] = wrapi(cx + 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
     up[1] = cx + (long)g.n[0] * (wrapi(cy + 1, g.n[1]) + (long)g.n[1] * cz);
     up[2] = D == 3 ? cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz + 1, g.n[2])) : 0;
+    // an upper non-periodic boundary face has its own flux
+    bool top[3];
+    long ptop[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        top[a] = !g.periodic && c[a] == g.n[a] - 1 && g.bc[a][1] != BC_PERIODIC;
+        ptop[a] = top[a] ? plane_index(a, cx, cy, cz, g.n) : 0;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double Fp = fbar[(a * NV + v) * g.ncell + up[a]];
+            const double Fp = top[a] ? fbar_top[(a * NV + v) * plane + ptop[a]] : fbar[(a * NV + v) * g.ncell + up[a]];
             const double Fm = fbar[(a * NV + v) * g.ncell + cell];
             acc -= (Fp - Fm) / g.dx[a];
         }
@@ -600,10 +664,12 @@ hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter
     mark(KT_RECON, 0);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     mark(KT_FLUX, 1);
-    hipLaunchKernelGGL((k_flux<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.face, w.theta, w.fbar, w.err, g, riemann);
+    hipLaunchKernelGGL((k_flux<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.face, w.theta, w.fbar, w.fbar_top, w.plane,
+                       w.err, g, riemann);
     mark(KT_FLUX, 0);
     mark(KT_UPDATE, 1);
-    hipLaunchKernelGGL((k_update<D>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
+    hipLaunchKernelGGL((k_update<D>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g, stage,
+                       dt);
     mark(KT_UPDATE, 0);
     return hipGetLastError();
 }
@@ -663,8 +729,12 @@ hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0
                          int stage, double dt, hipStream_t s)
 {
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
-    if (dim == 2) hipLaunchKernelGGL((k_update<2>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
-    else hipLaunchKernelGGL((k_update<3>), dim3(nb), dim3(256), 0, s, w.fbar, U0, Uin, out, g, stage, dt);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_update<2>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g,
+                           stage, dt);
+    else
+        hipLaunchKernelGGL((k_update<3>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g,
+                           stage, dt);
     return hipGetLastError();
 }
 

@@ -23,9 +23,11 @@ EXPORTED = [
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
     "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step", "kfvm_set_indicator", "kfvm_kxrcf",
+    "kfvm_set_boundary",
 ]
 KERNEL_CLASSES = ("recon", "flux", "update", "indicator")
 KFVM_IND_NONE, KFVM_IND_KXRCF = 0, 1
+BC_KINDS = {"periodic": 0, "outflow": 1, "reflecting": 2, "inflow": 3}
 
 
 class KfvmError(RuntimeError):
@@ -87,6 +89,7 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_mlp_train_step": ([vp, vp, vp, ip, vp, vp, vp, ip, C.c_float, C.c_float, vp, vp, vp], ip),
         "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
         "kfvm_set_indicator": ([vp, ip, C.c_double], ip),
+        "kfvm_set_boundary": ([vp, ip, ip, ip, dp, dp], ip),
         "kfvm_kxrcf": ([vp, vp, C.c_double, vp, vp], ip),
         "kfvm_destroy": ([vp], None),
     }
@@ -245,6 +248,17 @@ class KFVM:
             raise ValueError("flags must be a contiguous uint8 CUDA tensor of nvar * ncell entries")
         self._flags = flags
         self._check(self.lib.kfvm_set_flags(self._h, C.c_void_p(flags.data_ptr())))
+
+    def set_boundary(self, axis: int, lower: str, upper: str, lower_state=None, upper_state=None):
+        """Boundary conditions of one axis: "periodic" on both sides, or per side
+        "outflow", "reflecting", "inflow" (with its conserved state)."""
+        def arr(x):
+            if x is None:
+                return None
+            a = (C.c_double * self.nvar)(*[float(v) for v in x])
+            return C.cast(a, C.POINTER(C.c_double))
+        lo, hi = arr(lower_state), arr(upper_state)
+        self._check(self.lib.kfvm_set_boundary(self._h, int(axis), BC_KINDS[lower], BC_KINDS[upper], lo, hi))
 
     # -- KXRCF indicator -------------------------------------------------------
     def set_indicator(self, kind, m: float = 1.5):

@@ -1,0 +1,147 @@
+"""Outflow, reflecting and inflow boundaries on the GPU (FP64 path, through the
+C-ABI) against the oracle: right-hand side and limited states to 1e-12, the
+KXRCF jumps and decisions with boundary faces, a short trajectory, and the
+split-precision path refusing non-periodic grids."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_16543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(a, b):
+    nv = a.shape[0]
+    a, b = np.asarray(a).reshape(nv, -1), np.asarray(b).reshape(nv, -1)
+    return max(float(np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()) for k in range(nv))
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2401_16543_amd import kfvm
+    kfvm.load_library()
+    return kfvm
+
+
+def _inflow(d, seed):
+    rng = np.random.default_rng(seed)
+    rho, p = 0.8 + rng.random(), 0.5 + rng.random()
+    vel = rng.normal(0.0, 0.5, d)
+    return np.array([rho] + list(rho * vel) + [p / 0.4 + 0.5 * rho * (vel ** 2).sum()])
+
+
+def _state(d, n, kind, seed):
+    if kind == "jumps":
+        U = inputs.cell_averages(inputs.discontinuous(seed, d, 6 if d == 2 else 4, 10.0, 100.0), max(n), 1.4,
+                                 rule="midpoint", q=4 if d == 2 else 2)
+    else:
+        U = inputs.cell_averages(inputs.smooth(seed, d, 3), max(n), 1.4, rule="gauss", q=3)
+    return U[(slice(None),) + tuple(slice(0, x) for x in reversed(n))].contiguous()
+
+
+# (d, R, n, per-axis (lower, upper), kind)
+CASES = [
+    (2, 2, (37, 29), [("reflecting", "reflecting"), ("periodic", "periodic")], "jumps"),
+    (2, 2, (40, 36), [("inflow", "outflow"), ("reflecting", "reflecting")], "wave"),
+    (2, 3, (40, 36), [("outflow", "outflow"), ("reflecting", "outflow")], "jumps"),
+    (2, 2, (6, 20), [("reflecting", "reflecting"), ("inflow", "outflow")], "wave"),
+    (3, 2, (13, 11, 9), [("inflow", "outflow"), ("reflecting", "reflecting"), ("periodic", "periodic")], "jumps"),
+    (3, 3, (12, 10, 9), [("reflecting", "outflow"), ("outflow", "inflow"), ("reflecting", "reflecting")], "wave"),
+]
+
+
+def _setup(K, oracle_mod, d, R, n, bcs, seed, kxrcf=None):
+    dx = [1.0 / max(n)] * d
+    orc = oracle_mod.Oracle(d, R, n, dx=dx, kxrcf_m=kxrcf)
+    dev = K.KFVM(d, n, dx=dx, order=2 * R + 1)
+    dev.set_checking(True)
+    for a, (lo, hi) in enumerate(bcs):
+        sl = _inflow(d, seed + 2 * a) if lo == "inflow" else None
+        sh = _inflow(d, seed + 2 * a + 1) if hi == "inflow" else None
+        orc.set_boundary(a, lo, hi, lower_state=sl, upper_state=sh)
+        dev.set_boundary(a, lo, hi, lower_state=sl, upper_state=sh)
+    if kxrcf:
+        dev.set_indicator("kxrcf", kxrcf)
+    return orc, dev
+
+
+@pytest.mark.parametrize("d,R,n,bcs,kind", CASES)
+def test_boundary_rhs_matches_oracle(K, oracle_mod, d, R, n, bcs, kind):
+    say(f"case boundary rhs d={d} R={R} n={n} {bcs} {kind}")
+    U = _state(d, n, kind, 60 + d + R)
+    orc, dev = _setup(K, oracle_mod, d, R, n, bcs, 5)
+    Ud = U.cuda()
+    got = dev.rhs(Ud).cpu().numpy()
+    st = dev.face_states(Ud).cpu().numpy()
+    e_rhs = rel_err(got, orc.rhs(U.numpy()))
+    e_st = rel_err(np.moveaxis(st, -1, 0), np.moveaxis(orc.states(U.numpy()), -1, 0))
+    say(f"  rhs rel err {e_rhs:.3e}  states rel err {e_st:.3e}")
+    assert e_rhs <= 1e-12 and e_st <= 1e-12
+
+
+@pytest.mark.parametrize("d,R,n,bcs,kind", CASES)
+def test_boundary_kxrcf_matches_oracle(K, oracle_mod, d, R, n, bcs, kind):
+    """Jumps (upper faces; boundary faces against the outer state), decisions and
+    the two-pass right-hand side."""
+    say(f"case boundary kxrcf d={d} R={R} n={n} {bcs} {kind}")
+    U = _state(d, n, kind, 70 + d + R)
+    orc, dev = _setup(K, oracle_mod, d, R, n, bcs, 9, kxrcf=1.5)
+    f_o, meas, J_o = orc.kxrcf(U.numpy(), 1.5)
+    J, fl = dev.kxrcf(U.cuda(), 1.5)
+    J, fl = J.cpu().numpy(), fl.cpu().numpy()
+    Jup = np.stack([J_o[:, 2 * a + 1] for a in range(d)])
+    assert np.array_equal(~np.isfinite(Jup), ~np.isfinite(J))
+    fin = np.isfinite(J)
+    Ue = U.numpy().reshape(d + 2, -1)
+    p = 0.4 * (Ue[d + 1] - 0.5 * (Ue[1:1 + d] ** 2).sum(0) / Ue[0])
+    scale = (p / Ue[0] ** 1.4).max()
+    err = (np.abs(J[fin] - Jup[fin]) / (scale + Jup[fin])).max() if fin.any() else 0.0
+    thr = orc.kxrcf_threshold(1.5)
+    diff = fl[0].astype(bool) != ~(meas < thr)
+    assert np.all(np.abs(meas[diff] / thr - 1.0) <= 1e-9)
+    Ud = U.cuda()
+    got = dev.rhs(Ud).cpu().numpy()
+    if diff.any():
+        orc.set_kxrcf(None)
+        orc.set_flags(fl)
+    e = rel_err(got, orc.rhs(U.numpy()))
+    say(f"  flagged {fl[0].mean():.3f}  jump err {err:.2e}  rhs rel err {e:.3e}")
+    assert err <= 1e-11 and e <= 1e-12
+
+
+def test_boundary_trajectory_matches_oracle(K, oracle_mod):
+    """10 SSP-RK3 steps of a small channel: inflow, outflow, reflecting walls,
+    the two-pass reconstruction."""
+    say("case boundary trajectory")
+    d, R, n = 2, 2, (48, 24)
+    U0 = _state(d, n, "wave", 31)
+    bcs = [("inflow", "outflow"), ("reflecting", "reflecting")]
+    orc, dev = _setup(K, oracle_mod, d, R, n, bcs, 13, kxrcf=1.5)
+    Uo, Ug = U0.numpy().copy(), U0.cuda()
+    for _ in range(10):
+        dt = orc.cfl_dt(Uo, 0.4)
+        Uo = orc.step(Uo, dt)
+        dev.step(Ug, dt)
+    e = rel_err(Ug.cpu().numpy(), Uo)
+    say(f"  10-step rel err {e:.3e}")
+    assert e <= 1e-11
+
+
+def test_split_precision_refuses_non_periodic_grids(K):
+    say("case boundary split refusal")
+    dev = K.KFVM(2, (32, 32), order=5)
+    dev.set_boundary(0, "outflow", "outflow")
+    with pytest.raises(K.KfvmError):
+        dev.set_precision("split_f16")
+    dev2 = K.KFVM(2, (32, 32), order=5)
+    dev2.set_precision("split_f16")
+    with pytest.raises(K.KfvmError):
+        dev2.set_boundary(1, "reflecting", "reflecting")
+    with pytest.raises(K.KfvmError):
+        dev2.set_boundary(1, "periodic", "reflecting")
+    dev2.set_boundary(1, "periodic", "periodic")             # stays allowed
