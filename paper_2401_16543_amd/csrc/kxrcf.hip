@@ -17,9 +17,9 @@
 //          rho is within 1/32 of rho_c (pow otherwise), and the face maximum is
 //          scaled by rho_c^-gamma once.  Reads of a member group are issued one
 //          group ahead of the FMAs that use them.
-//   boundary  (non-periodic grids) one thread per cell: at the faces on a
-//          non-periodic boundary, the jump between the cell's unlimited state
-//          and the outer state the boundary condition gives.
+//   boundary  (non-periodic grids) one thread per boundary face: the jump
+//          between the cell's unlimited state and the outer state the
+//          boundary condition gives.
 //   flags  one thread per cell: the largest jump over its 2d faces against
 //          Delta^m times the entropy of its own average.  Every variable of a
 //          flagged cell takes WENO-AO in the reconstruction that follows, the
@@ -203,9 +203,17 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
     // one conditional wrap reaches every halo index once each axis holds a tile
     // plus R + 1 cells; smaller grids take the full modulo
     const bool near = g.n[0] >= C::TX + R + 1 && g.n[1] >= C::TY + R + 1 && (D == 2 || g.n[2] >= C::TZ + R + 1);
+    // only a tile whose halo crosses a non-periodic boundary needs the ghost fill
+    bool ghosts = false;
+    if (!g.periodic) {
+        const int o[3] = {x0, y0, z0}, h[3] = {C::HX, C::HY, C::HZ};
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            ghosts = ghosts || (g.bc[a][0] != BC_PERIODIC && (o[a] < 0 || o[a] + h[a] > g.n[a]));
+    }
     for (int i = threadIdx.x; i < C::HN; i += C::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        if (!g.periodic) {
+        if (ghosts) {
             // non-periodic axes: ghost cells by the boundary conditions (the
             // jumps of boundary faces are redone by k_kxrcf_boundary)
             double u[NV];
@@ -329,9 +337,10 @@ __global__ __launch_bounds__((KxCfg<D, R>::NT)) void k_kxrcf_jump(const double *
 
 // Jumps at the faces of non-periodic boundaries, between the cell's unlimited
 // state and the outer state the boundary condition gives (section 5.3, step 4):
-// upper faces overwrite J, lower faces go to Jlo.  One thread per cell; the
-// stencil is read through the ghost fill and the S0 rows of the FP64 tables.
-template <int D, int R>
+// upper faces overwrite J, lower faces go to Jlo.  One thread per boundary
+// face, the faces of axis A and side SIDE; the stencil is read through the
+// ghost fill and the S0 rows of the FP64 tables.
+template <int D, int R, int A, int SIDE>
 __global__ __launch_bounds__(256) void k_kxrcf_boundary(const double *__restrict__ U, const double *__restrict__ w0,
                                                       double *__restrict__ J, double *__restrict__ Jlo, long plane,
                                                       Geom g)
@@ -339,42 +348,52 @@ __global__ __launch_bounds__(256) void k_kxrcf_boundary(const double *__restrict
     using S = Stencil<D, R>;
     constexpr S st{};
     constexpr int NV = D + 2, NG = S::NG, N0 = S::N0;
-    const long cell = (long)blockIdx.x * 256 + threadIdx.x;
-    if (cell >= g.ncell) return;
-    const int c[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+    constexpr int B0 = A == 0 ? 1 : 0, B1 = A == 2 ? 1 : 2;          // the plane's axes, lower first
+    const long pi = (long)blockIdx.x * 256 + threadIdx.x;
+    const long np = g.ncell / g.n[A];
+    if (pi >= np) return;
+    int c[3] = {0, 0, 0};
+    c[B0] = (int)(pi % g.n[B0]);
+    c[B1] = D == 3 ? (int)(pi / g.n[B0]) : 0;
+    c[A] = SIDE ? g.n[A] - 1 : 0;
+    const long cell = c[0] + (long)g.n[0] * (c[1] + (long)g.n[1] * c[2]);
+    double jm = 0.0;
+    bool bad = false;
 #pragma unroll 1
-    for (int a = 0; a < D; ++a)
-#pragma unroll 1
-        for (int side = 0; side < 2; ++side) {
-            if (g.bc[a][side] == BC_PERIODIC || c[a] != (side ? g.n[a] - 1 : 0)) continue;
-            double jm = 0.0;
-            bool bad = false;
-#pragma unroll 1
-            for (int p = 0; p < NG; ++p) {
-                const double *row = w0 + ((2 * a + side) * NG + p) * N0;
-                double in[NV], out[NV];
+    for (int p = 0; p < NG; ++p) {
+        const double *row = w0 + ((2 * A + SIDE) * NG + p) * N0;
+        double in[NV], out[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) in[v] = 0.0;
-                int cx = c[0];
+        for (int v = 0; v < NV; ++v) in[v] = 0.0;
+        int cx = c[0];
 #pragma unroll
-                for (int j = 0; j < N0; ++j) {
-                    double u[NV];
-                    ghost_load<D>(U, g, cx + st.off[j][0], c[1] + st.off[j][1], c[2] + st.off[j][2], u);
+        for (int j = 0; j < N0; ++j) {
+            double u[NV];
+            ghost_load<D>(U, g, cx + st.off[j][0], c[1] + st.off[j][1], c[2] + st.off[j][2], u);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) in[v] = fma(row[j], u[v], in[v]);
-                    // the next member's address depends on this one's sums (empty
-                    // asm): one member's loads in flight, not all N0 hoisted
-                    asm volatile("" : "+v"(cx) : "v"(in[NV - 1]));
-                }
-                boundary_state<D>(g, a, side, in, out);
-                double qi = 0.0, qo = 0.0;
-                bad = bad || !point_entropy<D>(in, g.gamma, qi) || !point_entropy<D>(out, g.gamma, qo);
-                jm = fmax(jm, fabs(qo - qi));
-            }
-            const double j = bad ? INFINITY : jm;
-            if (side) J[(long)a * g.ncell + cell] = j;
-            else Jlo[(long)a * plane + plane_index(a, c[0], c[1], c[2], g.n)] = j;
+            for (int v = 0; v < NV; ++v) in[v] = fma(row[j], u[v], in[v]);
+            // the next member's address depends on this one's sums (empty asm):
+            // one member's loads in flight, not all N0 hoisted
+            asm volatile("" : "+v"(cx) : "v"(in[NV - 1]));
         }
+        boundary_state<D>(g, A, SIDE, in, out);
+        double qi = 0.0, qo = 0.0;
+        bad = bad || !point_entropy<D>(in, g.gamma, qi) || !point_entropy<D>(out, g.gamma, qo);
+        jm = fmax(jm, fabs(qo - qi));
+    }
+    const double j = bad ? INFINITY : jm;
+    if (SIDE) J[(long)A * g.ncell + cell] = j;
+    else Jlo[(long)A * plane + pi] = j;
+}
+
+template <int D, int R, int A>
+void launch_boundary_axis(const Geom &g, const double *U, const double *w0, double *J, double *Jlo, long plane,
+                          hipStream_t s)
+{
+    if (A >= D || g.bc[A][0] == BC_PERIODIC) return;
+    const unsigned nb = (unsigned)((g.ncell / g.n[A] + 255) / 256);
+    hipLaunchKernelGGL((k_kxrcf_boundary<D, R, A, 0>), dim3(nb), dim3(256), 0, s, U, w0, J, Jlo, plane, g);
+    hipLaunchKernelGGL((k_kxrcf_boundary<D, R, A, 1>), dim3(nb), dim3(256), 0, s, U, w0, J, Jlo, plane, g);
 }
 
 template <int D>
@@ -420,8 +439,11 @@ hipError_t kxrcf_impl(const Geom &g, const double *kw, const double *w0, const d
     hipLaunchKernelGGL((k_kxrcf_jump<D, R>), dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(C::NT), 0, s, U, kw, J, g,
                        ser);
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
-    if (!g.periodic)
-        hipLaunchKernelGGL((k_kxrcf_boundary<D, R>), dim3(nb), dim3(256), 0, s, U, w0, J, Jlo, plane, g);
+    if (!g.periodic) {
+        launch_boundary_axis<D, R, 0>(g, U, w0, J, Jlo, plane, s);
+        launch_boundary_axis<D, R, 1>(g, U, w0, J, Jlo, plane, s);
+        launch_boundary_axis<D, R, 2>(g, U, w0, J, Jlo, plane, s);
+    }
     if (flags)
         hipLaunchKernelGGL((k_kxrcf_flags<D>), dim3(nb), dim3(256), 0, s, U, J, Jlo, plane, flags, g, thr);
     return hipGetLastError();

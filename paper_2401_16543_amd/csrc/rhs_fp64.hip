@@ -301,9 +301,17 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     // a single conditional wrap reaches every halo index once the grid is at
     // least a tile plus R wide along each axis; smaller grids take the modulo
     const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
+    // only a tile whose halo crosses a non-periodic boundary needs the ghost fill
+    bool ghosts = false;
+    if (!g.periodic) {
+        const int o[3] = {x0, y0, z0}, h[3] = {C::HX, C::HY, C::HZ};
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            ghosts = ghosts || (g.bc[a][0] != BC_PERIODIC && (o[a] < 0 || o[a] + h[a] > g.n[a]));
+    }
     for (int i = threadIdx.x; i < C::HN; i += C::NT) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        if (!g.periodic) {
+        if (ghosts) {
             // non-periodic axes: ghost cells by the boundary conditions
             double u[NV];
             ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u);

@@ -276,3 +276,47 @@ def sod(config: str, R: int, device="cpu"):
             p += ww * np.where(left, SOD_LEFT[1], SOD_RIGHT[1])
     U = np.stack([rho, np.zeros_like(rho), np.zeros_like(rho), p / (SOD_GAMMA - 1.0)])
     return torch.from_numpy(U).to(device), {"n": (nx, ny), "dx": h}
+
+
+# ----------------------------------------------- Richtmyer-Meshkov instability ---
+RMI_MA, RMI_RHO_D, RMI_GAMMA = 3.0, 2.0, 1.4
+RMI_X0, RMI_X1 = -0.5, 5.5          # domain [-1/2, 11/2] x [0, 1]
+
+
+def rmi_primitive(x, y, gamma=RMI_GAMMA, ma=RMI_MA, rho_d=RMI_RHO_D):
+    """(rho, u, v, p) of the Richtmyer-Meshkov initial state (section 6.3): the
+    post-shock state of a Mach-ma shock for x < 0.2, then density 1 for x < y and
+    rho_d for x >= y at rest with p = 1."""
+    post = x < 0.2
+    rho_s = 1.0 / (1.0 - 2.0 / (gamma + 1.0) * (1.0 - 1.0 / ma ** 2))
+    rho = np.where(post, rho_s, np.where(x < y, 1.0, rho_d))
+    p = np.where(post, 1.0 + 2.0 * gamma / (gamma + 1.0) * (ma ** 2 - 1.0), 1.0)
+    u = np.where(post, ma * math.sqrt(gamma) * (1.0 - 1.0 / rho_s), 0.0)
+    return rho, u, np.zeros_like(rho), p
+
+
+def rmi_inflow_state(gamma=RMI_GAMMA):
+    """Conserved post-shock state fixed at the inflow boundary x = -1/2."""
+    rho, u, v, p = (float(a) for a in rmi_primitive(np.array(-0.5), np.array(0.5), gamma))
+    return np.array([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def rmi(R: int, cells_per_unit: int = 512, device="cpu"):
+    """Cell averages of the Richtmyer-Meshkov problem on [-1/2, 11/2] x [0, 1] with
+    spacing 1 / cells_per_unit (the paper's 1/512: 3072 x 512 cells), by the
+    tensor Gauss rule with R points per axis.  Boundaries: fixed inflow at
+    x = -1/2, extrapolation (outflow) at x = 11/2, reflecting in y.
+    Returns (U [4, ny, nx] float64 tensor, dict(n, dx, inflow))."""
+    h = 1.0 / cells_per_unit
+    nx, ny = int(round((RMI_X1 - RMI_X0) * cells_per_unit)), cells_per_unit
+    g, w = np.polynomial.legendre.leggauss(R)
+    xc = RMI_X0 + (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    Y, X = np.meshgrid(yc, xc, indexing="ij")
+    acc = np.zeros((4, ny, nx))
+    for gy, wy in zip(g, w):
+        for gx, wx in zip(g, w):
+            rho, u, v, p = rmi_primitive(X + 0.5 * gx * h, Y + 0.5 * gy * h)
+            ww = 0.25 * wx * wy
+            acc += ww * np.stack([rho, rho * u, rho * v, p / (RMI_GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)])
+    return torch.from_numpy(acc).to(device), {"n": (nx, ny), "dx": h, "inflow": rmi_inflow_state()}
