@@ -8,7 +8,7 @@
  * and advances it with the three-stage SSP Runge-Kutta method of Shu & Osher.
  *
  * Boundaries are periodic unless kfvm_set_boundary says otherwise (outflow,
- * reflecting, inflow; FP64 path).
+ * reflecting, inflow).
  *
  * The right-hand side follows the paper's section 5.3: per cell the linearised
  * primitive variables W = Phi U with Phi from the cell's own average (section
@@ -133,7 +133,7 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
  * nonlinear-weight normalisation, the limiter, the Riemann solver and the
  * Runge-Kutta update stay in float64.  The split modes need fewer than 2^30
- * cells and a periodic grid (KFVM_ERR_ARG otherwise). */
+ * cells (KFVM_ERR_ARG otherwise). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 
 /* Boundary conditions of one axis (section 5.3: ghost cells filled by them,
@@ -149,10 +149,10 @@ int kfvm_set_precision(kfvm_ctx *ctx, int mode);
  * At a corner ghost cell the first inflow axis in x, y, z order gives the state,
  * otherwise every axis clamps or mirrors its index; the normal momentum of every
  * reflecting axis is then negated.  The KXRCF jump at a boundary face is taken
- * against the outer state.  Non-periodic grids run on the FP64 path only
- * (KFVM_ERR_ARG in a split mode; kfvm_set_precision refuses the split modes on
- * them).  Errors: KFVM_ERR_ARG (axis, kind, periodic on one side only, missing
- * inflow state), KFVM_ERR_NONPHYSICAL (an inflow state with rho <= 0 or p <= 0).
+ * against the outer state; the learned gate sees the ghost-filled averages.
+ * Every precision mode supports them.  Errors: KFVM_ERR_ARG (axis, kind,
+ * periodic on one side only, missing inflow state), KFVM_ERR_NONPHYSICAL (an
+ * inflow state with rho <= 0 or p <= 0).
  * The first non-periodic axis allocates dim * nvar * (largest boundary plane)
  * float64 of boundary-face fluxes. */
 int kfvm_set_boundary(kfvm_ctx *ctx, int axis, int lower, int upper, const double *lower_state,

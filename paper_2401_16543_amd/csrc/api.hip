@@ -536,7 +536,6 @@ int kfvm_set_precision(kfvm_ctx *c, int mode)
     if (mode != KFVM_FP64) {
         if (!kfvm::mixed_supported(c->dim, c->R))
             return fail(c, KFVM_ERR_ARG, "split precision is not available for this dimension and order");
-        if (!c->geom.periodic) return fail(c, KFVM_ERR_ARG, "the split-precision path takes periodic grids only");
         const int rc = prepare_mixed(c, mode);
         if (rc != KFVM_OK) return rc;
     }
@@ -635,8 +634,6 @@ int kfvm_set_boundary(kfvm_ctx *c, int axis, int lower, int upper, const double 
             return fail(c, KFVM_ERR_ARG, "unknown boundary condition");
     if ((lower == KFVM_BC_PERIODIC) != (upper == KFVM_BC_PERIODIC))
         return fail(c, KFVM_ERR_ARG, "periodic must be set on both sides of an axis");
-    if (lower != KFVM_BC_PERIODIC && c->precision != KFVM_FP64)
-        return fail(c, KFVM_ERR_ARG, "the split-precision path takes periodic grids only");
     for (int side = 0; side < 2; ++side) {
         if (kinds[side] != KFVM_BC_INFLOW) continue;
         if (!states[side]) return fail(c, KFVM_ERR_ARG, "an inflow side needs its state");

@@ -106,6 +106,21 @@ __device__ __forceinline__ void ghost_load(const double *__restrict__ U, const G
         if (flip[a]) u[1 + a] = -u[1 + a];
 }
 
+// The cell a ghost coordinate i of axis a copies (inflow ghosts: the nearest
+// interior cell), for per-cell data other than the averages.
+__device__ __forceinline__ int ghost_index(const Geom &g, int a, int i)
+{
+    const int n = g.n[a];
+    if (i >= 0 && i < n) return i;
+    const int side = i < 0 ? 0 : 1, kind = g.bc[a][side];
+    if (kind == BC_PERIODIC) {
+        const int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    if (kind == BC_REFLECTING) return min(max(side ? 2 * n - 1 - i : -1 - i, 0), n - 1);
+    return side ? n - 1 : 0;
+}
+
 // Riemann state outside the domain at a boundary face of axis a (section 5.3,
 // step 4) from the inner one: the same (outflow), normal momentum negated
 // (reflecting) or the given state (inflow).

@@ -494,8 +494,8 @@ __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::
      ...);
 }
 
-// Tile of conserved averages plus its R-cell halo (periodic wrap = ghost fill)
-// into LDS; with the limiter on, also each tile cell's pressure (-1 where the
+// Tile of conserved averages plus its R-cell halo (the ghost fill: periodic
+// wrap, or the boundary conditions of non-periodic axes) into LDS; with the limiter on, also each tile cell's pressure (-1 where the
 // average is not admissible) for the neighbourhood bounds.
 template <int D, int R, int NTHR, typename PT>
 __device__ __forceinline__ void load_tile(const double *__restrict__ U, const Geom &g, const Limiter &lim, int x0,
@@ -507,17 +507,31 @@ __device__ __forceinline__ void load_tile(const double *__restrict__ U, const Ge
     // a single conditional wrap reaches every halo index once the grid is at
     // least a tile plus R wide along each axis; smaller grids take the modulo
     const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
+    // only a tile whose halo crosses a non-periodic boundary needs the ghost fill
+    bool ghosts = false;
+    if (!g.periodic) {
+        const int o[3] = {x0, y0, z0}, h[3] = {C::HX, C::HY, C::HZ};
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            ghosts = ghosts || (g.bc[a][0] != BC_PERIODIC && (o[a] < 0 || o[a] + h[a] > g.n[a]));
+    }
     for (int i = threadIdx.x; i < C::HN; i += NTHR) {
         const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
-        const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
-        const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
-        const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
         double u[NV];
+        if (ghosts) {
+            ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            u[v] = U[v * g.ncell + cl];
-            tile[v][i] = u[v];
+            for (int v = 0; v < NV; ++v) tile[v][i] = u[v];
+        } else {
+            const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
+            const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
+            const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
+            const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                u[v] = U[v * g.ncell + cl];
+                tile[v][i] = u[v];
+            }
         }
         if (lim.on) {
             double mm = 0.0;
@@ -1040,8 +1054,9 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     if constexpr (GATE) {
         for (int i = threadIdx.x; i < GX * GY * GZ; i += M::NT) {
             const int hx = i % GX, hy = (i / GX) % GY, hz = i / (GX * GY);
-            const int gx = wrap_any(bx * C::TX - 1 + hx, g.n[0]), gy = wrap_any(by * C::TY - 1 + hy, g.n[1]);
-            const int gz = D == 3 ? wrap_any(bz * C::TZ - 1 + hz, g.n[2]) : 0;
+            // (past a non-periodic boundary: the decisions of the cell the ghost copies)
+            const int gx = ghost_index(g, 0, bx * C::TX - 1 + hx), gy = ghost_index(g, 1, by * C::TY - 1 + hy);
+            const int gz = D == 3 ? ghost_index(g, 2, bz * C::TZ - 1 + hz) : 0;
             gtile[i] = ga.raw[gx + (long)g.n[0] * (gy + (long)g.n[1] * gz)];
         }
     }
@@ -1130,9 +1145,72 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
     }
 }
 
+// Flux through the face of `cell` on this side of axis A when it lies on a
+// non-periodic boundary: the cell's limited state inside, the state the
+// boundary condition gives outside (section 5.3, step 4).
+template <int D, int R, int A>
+__device__ __forceinline__ void boundary_face_flux_mixed(const float *__restrict__ inc, const Geom &g, long cell,
+                                                         int side, const double *ref, const PhiInv<D> &pi, double th,
+                                                         int hll, double *Fbar)
+{
+    using S = Stencil<D, R>;
+    constexpr int NV = D + 2, NG = S::NG;
+    const float *incc = inc + cell;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
+#pragma unroll 1
+    for (int gi = 0; gi < NG; ++gi) {
+        double w[NV], d[NV], in[NV], out[NV], F[NV];
+        const long s = (long)((2 * A + side) * NG + gi) * NV * g.ncell;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = (double)incc[s + v * g.ncell];
+        pi.apply(w, d);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) in[v] = ref[v] + th * d[v];
+        boundary_state<D>(g, A, side, in, out);
+        if (side) riemann<D, A>(in, out, g.gamma, hll, F);
+        else riemann<D, A>(out, in, g.gamma, hll, F);
+        const double wt = face_weight<D, R>(gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[v] += wt * F[v];
+    }
+}
+
+// The fluxes of axis A at `cell`: its lower face into fbar and, on an upper
+// non-periodic boundary, its upper face into fbar_top.
+template <int D, int R, int A>
+__device__ __forceinline__ bool axis_fluxes_mixed(const double *__restrict__ U, const float *__restrict__ inc,
+                                                  const double *__restrict__ theta, double *__restrict__ fbar,
+                                                  double *__restrict__ fbar_top, long plane, const Geom &g, long cell,
+                                                  const int *c, const double *refR, const PhiInv<D> &piR, double thR,
+                                                  int hll)
+{
+    constexpr int NV = D + 2;
+    double F[NV];
+    bool ok = true;
+    if (!g.periodic && c[A] == 0 && g.bc[A][0] != BC_PERIODIC) {
+        boundary_face_flux_mixed<D, R, A>(inc, g, cell, 0, refR, piR, thR, hll, F);
+    } else {
+        int lc[3] = {c[0], c[1], c[2]};
+        lc[A] = wrapi(c[A] - 1, g.n[A]);
+        const long lower = lc[0] + (long)g.n[0] * (lc[1] + (long)g.n[1] * lc[2]);
+        lower_face_flux_mixed<D, R, A>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { fbar[(A * NV + v) * g.ncell + cell] = F[v]; ok = ok && isfinite(F[v]); }
+    if (!g.periodic && c[A] == g.n[A] - 1 && g.bc[A][1] != BC_PERIODIC) {
+        boundary_face_flux_mixed<D, R, A>(inc, g, cell, 1, refR, piR, thR, hll, F);
+        const long pi = plane_index(A, c[0], c[1], c[2], g.n);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { fbar_top[(A * NV + v) * plane + pi] = F[v]; ok = ok && isfinite(F[v]); }
+    }
+    return ok;
+}
+
 template <int D, int R>
 __global__ __launch_bounds__(256) void k_flux_mixed(const double *__restrict__ U, const float *__restrict__ inc,
                                                     const double *__restrict__ theta, double *__restrict__ fbar,
+                                                    double *__restrict__ fbar_top, long plane,
                                                     int *__restrict__ err, Geom g, int hll)
 {
     constexpr int NV = D + 2;
@@ -1146,27 +1224,11 @@ __global__ __launch_bounds__(256) void k_flux_mixed(const double *__restrict__ U
     const double thR = theta[cell] * theta[g.ncell + cell];
     PhiInv<D> piR;
     piR.init(refR, g.gamma);
-    double *fb = fbar + cell;
-    double F[NV];
-    bool ok = true;
-    {
-        const long lower = wrapi(cx - 1, g.n[0]) + (long)g.n[0] * (cy + (long)g.n[1] * cz);
-        lower_face_flux_mixed<D, R, 0>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fb[(0 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
-    {
-        const long lower = cx + (long)g.n[0] * (wrapi(cy - 1, g.n[1]) + (long)g.n[1] * cz);
-        lower_face_flux_mixed<D, R, 1>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fb[(1 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
-    if constexpr (D == 3) {
-        const long lower = cx + (long)g.n[0] * (cy + (long)g.n[1] * wrapi(cz - 1, g.n[2]));
-        lower_face_flux_mixed<D, R, 2>(U, inc, theta, g, cell, lower, refR, piR, thR, hll, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { fb[(2 * NV + v) * g.ncell] = F[v]; ok = ok && isfinite(F[v]); }
-    }
+    const int c[3] = {cx, cy, cz};
+    bool ok = axis_fluxes_mixed<D, R, 0>(U, inc, theta, fbar, fbar_top, plane, g, cell, c, refR, piR, thR, hll);
+    ok = axis_fluxes_mixed<D, R, 1>(U, inc, theta, fbar, fbar_top, plane, g, cell, c, refR, piR, thR, hll) && ok;
+    if constexpr (D == 3)
+        ok = axis_fluxes_mixed<D, R, 2>(U, inc, theta, fbar, fbar_top, plane, g, cell, c, refR, piR, thR, hll) && ok;
     if (!ok) *err = ERR_NONPHYSICAL;
 }
 
@@ -1236,8 +1298,8 @@ hipError_t mixed_impl(const Geom &g, const MixTables &t, const Work &w, const Li
         return hipGetLastError();
     }
     mark(KT_FLUX, 1);
-    hipLaunchKernelGGL((k_flux_mixed<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.inc32, w.theta, w.fbar, w.err, g,
-                       riemann);
+    hipLaunchKernelGGL((k_flux_mixed<D, R>), dim3(nb), dim3(256), 0, s, Uin, w.inc32, w.theta, w.fbar, w.fbar_top,
+                       w.plane, w.err, g, riemann);
     mark(KT_FLUX, 0);
     mark(KT_UPDATE, 1);
     hipError_t e = launch_update(D, g, w, U0, Uin, out, stage, dt, s);

@@ -1,7 +1,7 @@
-"""Outflow, reflecting and inflow boundaries on the GPU (FP64 path, through the
-C-ABI) against the oracle: right-hand side and limited states to 1e-12, the
+"""Outflow, reflecting and inflow boundaries on the GPU (through the C-ABI)
+against the oracle: the FP64 right-hand side and limited states to 1e-12, the
 KXRCF jumps and decisions with boundary faces, a short trajectory, and the
-split-precision path refusing non-periodic grids."""
+split-precision path (with and without the learned gate) to its accuracy bar."""
 import numpy as np
 import pytest
 import torch
@@ -132,16 +132,37 @@ def test_boundary_trajectory_matches_oracle(K, oracle_mod):
     assert e <= 1e-11
 
 
-def test_split_precision_refuses_non_periodic_grids(K):
-    say("case boundary split refusal")
-    dev = K.KFVM(2, (32, 32), order=5)
-    dev.set_boundary(0, "outflow", "outflow")
-    with pytest.raises(K.KfvmError):
-        dev.set_precision("split_f16")
-    dev2 = K.KFVM(2, (32, 32), order=5)
-    dev2.set_precision("split_f16")
-    with pytest.raises(K.KfvmError):
-        dev2.set_boundary(1, "reflecting", "reflecting")
-    with pytest.raises(K.KfvmError):
-        dev2.set_boundary(1, "periodic", "reflecting")
-    dev2.set_boundary(1, "periodic", "periodic")             # stays allowed
+@pytest.mark.parametrize("d,R,n,bcs,kind", CASES)
+@pytest.mark.parametrize("mode,tol", [("split_f16", 2e-5), ("split_bf16", 2e-2)])
+def test_boundary_split_precision(K, oracle_mod, d, R, n, bcs, kind, mode, tol):
+    """The split-precision path with the same boundaries: its accuracy bar."""
+    say(f"case boundary {mode} d={d} R={R} n={n} {bcs} {kind}")
+    U = _state(d, n, kind, 60 + d + R)
+    orc, dev = _setup(K, oracle_mod, d, R, n, bcs, 5)
+    dev.set_precision(mode)
+    e = rel_err(dev.rhs(U.cuda()).cpu().numpy(), orc.rhs(U.numpy()))
+    say(f"  rhs rel err {e:.3e}")
+    assert e <= tol
+
+
+@pytest.mark.parametrize("d,R", [(2, 2), (3, 2), (3, 3)])
+def test_boundary_gated_split_precision(K, oracle_mod, d, R):
+    """The learned gate next to boundaries (its inputs come from the ghost-filled
+    tile); the oracle replays the decisions."""
+    from paper_2401_16543_amd import gate
+    say(f"case boundary gate d={d} R={R}")
+    n = (40, 36) if d == 2 else (16, 12, 10)
+    bcs = [("inflow", "outflow"), ("reflecting", "reflecting")] + ([("outflow", "reflecting")] if d == 3 else [])
+    U = _state(d, n, "jumps", 80 + d + R)
+    orc, dev = _setup(K, oracle_mod, d, R, n, bcs, 17)
+    dev.set_precision("split_f16")
+    params, thr, _ = gate.load(d)
+    dev.set_gate(torch.from_numpy(params).cuda(), thr)
+    got = dev.rhs(U.cuda()).cpu().numpy()
+    fl = dev.get_flags().cpu().numpy()
+    orc.set_flags(fl)
+    e = rel_err(got, orc.rhs(U.numpy()))
+    say(f"  flagged {fl.mean():.3f}  rhs rel err {e:.3e}")
+    if R == 2:          # (order 7 dilates the decisions over 3^3 blocks: this field is all WENO-AO)
+        assert 0.0 < fl.mean() < 1.0
+    assert e <= 2e-5
