@@ -1,11 +1,12 @@
 """The Richtmyer-Meshkov run of section 6.3 on one GPU through the library.
 
     python -m paper_2401_16543_amd.rmi [--R 2] [--cells-per-unit 512] [--t-end 3.33]
-                                       [--cfl 0.5] [--no-indicator]
+                                       [--cfl 0.5] [--no-indicator] [--precision fp64]
+                                       [--compare-fp64]
 
 Domain [-1/2, 11/2] x [0, 1] at spacing 1/512 (3072 x 512 cells), Mach-3 shock
 into an oblique density jump (rho_D = 2), fixed inflow at x = -1/2, outflow at
-x = 11/2, reflecting walls in y; the FP64 path, SSP-RK3 at a fixed CFL number
+x = 11/2, reflecting walls in y; any precision path, SSP-RK3 at a fixed CFL number
 (the paper integrates with its adaptive SSP(4,3,2)), with or without the KXRCF
 two-pass reconstruction (m = 3/2).  Prints a progress line every few hundred
 steps and one JSON summary: right-hand-side evaluations, wall time per
@@ -21,7 +22,10 @@ import time
 
 
 def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float = 0.5, indicator: bool = True,
-        report_every: int = 500, max_steps: int | None = None) -> dict:
+        report_every: int = 500, max_steps: int | None = None, precision: str = "fp64", keep_state: bool = False,
+        dts=None) -> dict:
+    """One run; `dts` replays a recorded sequence of step sizes (the summary's
+    "dts" when keep_state is set) so that two runs can be compared state for state."""
     import torch
 
     from . import inputs, kfvm
@@ -31,6 +35,7 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
     dev = kfvm.KFVM(2, (nx, ny), dx=[m["dx"]] * 2, order=2 * R + 1, gamma=inputs.RMI_GAMMA)
     dev.set_boundary(0, "inflow", "outflow", lower_state=m["inflow"])
     dev.set_boundary(1, "reflecting", "reflecting")
+    dev.set_precision(precision)
     if indicator:
         dev.set_indicator("kxrcf", 1.5)
     dev.set_timing(True)
@@ -44,9 +49,16 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
         for k, (ms, _) in dev.kernel_times().items():
             totals[k] = totals.get(k, 0.0) + ms
 
+    taken = []
     t0 = time.perf_counter()
     while t < t_end - 1e-12 and (max_steps is None or steps < max_steps):
-        dt = min(dev.cfl_dt(U, cfl), t_end - t)
+        if dts is not None:
+            if steps >= len(dts):
+                break
+            dt = dts[steps]
+        else:
+            dt = min(dev.cfl_dt(U, cfl), t_end - t)
+        taken.append(dt)
         dev.step(U, dt)
         t += dt
         steps += 1
@@ -59,12 +71,17 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
     collect()
     flagged = float(dev.get_flags()[0].float().mean()) if indicator else 1.0
     nrhs = 3 * steps
-    return {"problem": "Richtmyer-Meshkov, Ma 3, rho_D 2", "R": R, "grid": [nx, ny], "t": t, "steps": steps,
+    out = {"problem": "Richtmyer-Meshkov, Ma 3, rho_D 2", "R": R, "grid": [nx, ny], "t": t, "steps": steps,
+            "precision": precision,
             "rhs_evaluations": nrhs, "cfl": cfl, "indicator": "KXRCF m=3/2" if indicator else "none (WENO-AO everywhere)",
             "wall_s": wall, "wall_ms_per_rhs": wall / nrhs * 1e3,
             "device_ms_total": totals,
             "flagged_fraction_final": flagged, "status": status,
             "rho_range": [float(U[0].min()), float(U[0].max())]}
+    if keep_state:
+        out["U"] = U
+        out["dts"] = taken
+    return out
 
 
 def main():
@@ -75,8 +92,19 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.5)
     ap.add_argument("--no-indicator", action="store_true")
     ap.add_argument("--max-steps", type=int, default=None)
+    ap.add_argument("--precision", default="fp64", help="fp64, split_f16 or split_bf16")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also run the FP64 path with the same step sizes and report the L1 density difference")
     a = ap.parse_args()
-    out = run(a.R, a.cells_per_unit, a.t_end, a.cfl, not a.no_indicator, max_steps=a.max_steps)
+    out = run(a.R, a.cells_per_unit, a.t_end, a.cfl, not a.no_indicator, max_steps=a.max_steps,
+              precision=a.precision, keep_state=a.compare_fp64)
+    if a.compare_fp64:
+        ref = run(a.R, a.cells_per_unit, a.t_end, a.cfl, not a.no_indicator, precision="fp64", keep_state=True,
+                  dts=out["dts"])
+        out["l1_rho_vs_fp64"] = float((out["U"][0] - ref["U"][0]).abs().mean())
+        out["fp64_wall_ms_per_rhs"] = ref["wall_ms_per_rhs"]
+        out.pop("U")
+        out.pop("dts")
     print(json.dumps(out), flush=True)
 
 
