@@ -3,7 +3,7 @@
  *
  * The library evaluates the semi-discrete right-hand side of the compressible
  * Euler equations (paper section 1, eq. model and eq. euler, ideal-gas law with
- * ratio of specific heats gamma) on a periodic uniform Cartesian grid with the
+ * ratio of specific heats gamma) on a uniform Cartesian grid with the
  * kernel-based finite volume WENO-AO scheme of May & Lee (arXiv 2401.16543),
  * and advances it with the three-stage SSP Runge-Kutta method of Shu & Osher.
  *

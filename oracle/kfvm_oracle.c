@@ -1,7 +1,8 @@
 /*
  * Oracle: KFVM-WENO right-hand side, positivity limiter, Riemann solvers and
- * SSP-RK3 step for the compressible Euler equations on a periodic uniform
- * Cartesian grid, in plain binary64 C.
+ * SSP-RK3 step for the compressible Euler equations on a uniform
+ * Cartesian grid (periodic, or with outflow, reflecting and inflow
+ * boundaries), in plain binary64 C.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link or call this
  * library; only the tests, the smoke check and the CPU-baseline leg of the
@@ -9,7 +10,8 @@
  *
  * It follows the paper's order of operations (section 5.3 "Time advancement"):
  * for every cell
- *   1. periodic ghost cells (index wrap);
+ *   1. ghost cells: index wrap on periodic axes, the boundary conditions on the
+ *      others (neighbor_state);
  *   2. Riemann states: the transformation matrix Phi of the linearised
  *      primitive variables from the cell's own average (section 3.4.2,
  *      eq. consToLPMat), W_h = Phi U_h over S0 (eq. consToRecVar), per
@@ -21,6 +23,8 @@
  *   3. the positivity limiter of section 4 (density scaling eq. ppThetaRho and
  *      eq. ppCorrectDens, pressure scaling by bisection eq. thetapRoot, eq. thetaP
  *      and eq. ppCorrectPres), with the flattener eta = 0 and kappa a parameter;
+ *   4. Riemann states outside the domain from the inner ones at boundary
+ *      faces (ghost_face_states);
  *   5. an approximate Riemann solver at every face Gauss point: HLLC (Toro,
  *      "Riemann Solvers and Numerical Methods for Fluid Dynamics", ch. 10) or HLL
  *      (Harten, Lax and van Leer 1983), with the wavespeed estimates of Batten et
