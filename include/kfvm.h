@@ -94,10 +94,13 @@ typedef struct {
     const double *gamma_lin;
 } kfvm_weights;
 
-/* Host-side statistics, filled by kfvm_stats (synchronising). */
+/* Host-side statistics, filled by kfvm_stats (synchronising), of the last
+ * reconstruction (the last kfvm_rhs, the last stage of kfvm_step, or the last
+ * kfvm_face_states). */
 typedef struct {
-    long long limiter_cells;     /* cells whose Riemann states the limiter scaled, last RHS */
-    long long weno_cell_vars;    /* (cell, variable) pairs reconstructed with WENO-AO, last RHS */
+    long long limiter_cells;     /* cells whose Riemann states the limiter scaled (a factor below one) */
+    long long weno_cell_vars;    /* (cell, variable) pairs reconstructed with WENO-AO (all of them unless a
+                                    gate, the indicator or kfvm_set_flags chose) */
     long long cell_vars;         /* all (cell, variable) pairs */
     int error;                   /* sticky device error code (0 or KFVM_ERR_NONPHYSICAL) */
 } kfvm_stats_t;

@@ -51,6 +51,8 @@ struct kfvm_ctx {
     double *d_kx_w = nullptr;       // S0 face rows as [axis][side][member][Gauss point]
     double *d_kx_jump = nullptr;    // [dim][ncell] largest entropy jump on each upper face
     double *d_kx_jlo = nullptr;     // [dim][plane] jumps on the lower faces of non-periodic boundaries
+    const uint8_t *last_flags = nullptr;   // the per-(variable, cell) choices of the last reconstruction
+    int recon_done = 0;                    // a reconstruction has filled the limiter factors
 };
 
 namespace {
@@ -298,7 +300,7 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     A((void **)&c->work.stage[1], sizeof(double) * (size_t)nv * ncell);
     A((void **)&c->work.cfl_part, sizeof(double) * 1024);
     A((void **)&c->work.err, sizeof(int) * 4);
-    A((void **)&c->work.counts, sizeof(uint32_t) * 4);
+    A((void **)&c->work.counts, sizeof(unsigned long long) * 2);
     A((void **)&c->d_dt, sizeof(double));
     if (rc != KFVM_OK) {
         g_init_msg = c->msg;
@@ -459,7 +461,10 @@ static int run_kxrcf(kfvm_ctx *c, const double *U, double m, double *J, uint8_t 
 static int prepare_flags(kfvm_ctx *c, const double *U, kfvm::Work &w)
 {
     w = c->work;
+    c->recon_done = 1;
+    c->last_flags = c->gate_on ? c->d_flags_out : c->work.flags_in;
     if (c->indicator != KFVM_IND_KXRCF) return KFVM_OK;
+    c->last_flags = c->d_flags_out;
     const int rc = run_kxrcf(c, U, c->kx_m, c->d_kx_jump, c->d_flags_out);
     w.flags_in = c->d_flags_out;
     return rc;
@@ -582,7 +587,20 @@ int kfvm_stats(kfvm_ctx *c, kfvm_stats_t *out)
     HIP_TRY(c, hipMemcpy(&err, c->work.err, sizeof(int), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     out->cell_vars = (long long)c->geom.ncell * c->nvar;
-    out->weno_cell_vars = out->cell_vars;
+    // counted from the limiter factors and the choices the last reconstruction left
+    unsigned long long cnt[2] = {0, 0};
+    if (!c->recon_done) {
+        out->error = err;
+        return KFVM_OK;
+    }
+    HIP_TRY(c, hipMemsetAsync(c->work.counts, 0, sizeof(cnt), c->stream));
+    hipError_t e = kfvm::launch_count_stats(c->work.theta, c->last_flags, c->geom.ncell, c->nvar, c->work.counts,
+                                            c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    HIP_TRY(c, hipMemcpyAsync(cnt, c->work.counts, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->limiter_cells = (long long)cnt[0];
+    out->weno_cell_vars = c->last_flags ? (long long)cnt[1] : out->cell_vars;
     out->error = err;
     return KFVM_OK;
 }

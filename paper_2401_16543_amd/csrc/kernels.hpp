@@ -32,7 +32,7 @@ struct Work {
     double *stage[2];  // [nvar][ncell] Runge-Kutta stage states
     double *cfl_part;  // per-block maxima of the CFL reduction
     int *err;          // sticky device error code
-    uint32_t *counts;  // [2] limiter cells, WENO (cell, var) pairs
+    unsigned long long *counts;  // [2] scratch of kfvm_stats: limiter cells, WENO (cell, var) pairs
     const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
     float *inc32;      // [n_pts][nvar][ncell] blended increments w_s - W_c (split-precision path)
     double *fbar_top;  // [dim][nvar][plane] fluxes through the upper boundary faces of non-periodic axes
@@ -100,6 +100,10 @@ hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, co
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s);
+// counts[0] += cells with a limiter factor below one (theta[2][ncell]);
+// counts[1] += nonzero bytes of flags[nvar][ncell] (skipped when flags is null)
+hipError_t launch_count_stats(const double *theta, const uint8_t *flags, long ncell, int nvar,
+                              unsigned long long *counts, hipStream_t s);
 
 // KXRCF indicator (kxrcf.hip): jumps J[dim][ncell] of the upper faces, then
 // (flags != nullptr) flags[nvar][ncell] = 1 where eq. kxrcf fails for threshold thr.

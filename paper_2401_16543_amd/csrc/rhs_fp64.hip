@@ -23,6 +23,8 @@
 // All arrays are struct-of-arrays over cells so that every global access is
 // coalesced along x.  Blocks are remapped so that each XCD owns a contiguous
 // run of tiles, which keeps halo re-reads in that XCD's L2.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace kfvm {
@@ -656,6 +658,28 @@ __global__ __launch_bounds__(256) void k_cfl_final(const double *__restrict__ pa
     }
 }
 
+// ------------------------------------------------------------ statistics ---
+__global__ __launch_bounds__(256) void k_count_stats(const double *__restrict__ theta,
+                                                     const uint8_t *__restrict__ flags, long ncell, int nvar,
+                                                     unsigned long long *__restrict__ counts)
+{
+    unsigned long long lim = 0, weno = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (long)gridDim.x * blockDim.x) {
+        lim += (theta[i] < 1.0 || theta[ncell + i] < 1.0) ? 1 : 0;
+        if (flags)
+            for (int v = 0; v < nvar; ++v) weno += flags[(long)v * ncell + i] != 0 ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lim += __shfl_xor(lim, off, 64);
+        weno += __shfl_xor(weno, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counts[0], lim);
+        atomicAdd(&counts[1], weno);
+    }
+}
+
 template <int D, int R>
 hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter &lim, int riemann,
                     const double *U0, const double *Uin, double *out, int stage, double dt, hipStream_t s,
@@ -731,6 +755,14 @@ hipError_t launch_recon_ratio(int dim, int R, const Geom &g, const Tables &t, co
     if (dim == 3 && R == 2) return ratio_impl<3, 2>(g, t, w, lim, U, ratio, s);
     if (dim == 3 && R == 3) return ratio_impl<3, 3>(g, t, w, lim, U, ratio, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_count_stats(const double *theta, const uint8_t *flags, long ncell, int nvar,
+                              unsigned long long *counts, hipStream_t s)
+{
+    const long nb = std::min<long>((ncell + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_stats, dim3((unsigned)nb), dim3(256), 0, s, theta, flags, ncell, nvar, counts);
+    return hipGetLastError();
 }
 
 hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0, const double *Uin, double *out,

@@ -166,3 +166,41 @@ def test_boundary_gated_split_precision(K, oracle_mod, d, R):
     if R == 2:          # (order 7 dilates the decisions over 3^3 blocks: this field is all WENO-AO)
         assert 0.0 < fl.mean() < 1.0
     assert e <= 2e-5
+
+
+@pytest.mark.parametrize("R,mode,tol", [(2, "fp64", 1e-12), (3, "fp64", 1e-12), (2, "split_f16", 2e-5)])
+def test_richtmyer_meshkov_full_size_sampled(K, oracle_mod, R, mode, tol):
+    """The paper's Richtmyer-Meshkov setup at full size (3072 x 512, inflow,
+    outflow and reflecting boundaries) with the two-pass reconstruction: the RHS
+    at sampled cells (corners, every boundary, the shock and the interface)
+    against the oracle replaying the GPU's decisions."""
+    say(f"case RMI full-size R={R} {mode}")
+    U, m = inputs.rmi(R)
+    nx, ny = m["n"]
+    dx = [m["dx"]] * 2
+    dev = K.KFVM(2, (nx, ny), dx=dx, order=2 * R + 1, gamma=inputs.RMI_GAMMA)
+    dev.set_boundary(0, "inflow", "outflow", lower_state=m["inflow"])
+    dev.set_boundary(1, "reflecting", "reflecting")
+    dev.set_precision(mode)
+    dev.set_indicator("kxrcf", 1.5)
+    dev.set_checking(True)
+    L = dev.rhs(U.cuda()).cpu().numpy().reshape(4, -1)
+    fl = dev.get_flags().cpu().numpy()
+    orc = oracle_mod.Oracle(2, R, (nx, ny), dx=dx, gamma=inputs.RMI_GAMMA)
+    orc.set_boundary(0, "inflow", "outflow", lower_state=m["inflow"])
+    orc.set_boundary(1, "reflecting", "reflecting")
+    orc.set_flags(fl)
+    rng = np.random.default_rng(3)
+    x0 = int(round((0.2 + 0.5) * 512))                        # the shock column
+    cells = np.concatenate([[0, nx - 1, nx * (ny - 1), nx * ny - 1],
+                            rng.integers(0, nx, 20),                            # lower wall
+                            nx * (ny - 1) + rng.integers(0, nx, 20),            # upper wall
+                            nx * rng.integers(0, ny, 20),                       # inflow side
+                            nx * rng.integers(0, ny, 20) + nx - 1,              # outflow side
+                            nx * rng.integers(0, ny, 40) + x0 + rng.integers(-3, 4, 40),
+                            np.flatnonzero(fl[0])[rng.integers(0, int(fl[0].sum()), 40)],
+                            rng.integers(0, nx * ny, 60)])
+    ref = orc.rhs_cells(U.numpy(), cells)
+    err = (np.abs(L[:, cells].T - ref) / np.abs(L).max(axis=1)).max()
+    say(f"  flagged {fl[0].mean():.4f}  sampled rel err {err:.3e}")
+    assert err <= tol

@@ -299,3 +299,28 @@ def test_two_pass_accuracy_on_exact_solution(K, case):
     assert kx.status() == K.KFVM_OK and plain.status() == K.KFVM_OK
     assert ek <= 1.05 * ep
     assert flagged < 0.5
+
+
+def test_stats_count_limited_cells_and_weno_pairs(K, oracle_mod):
+    """kfvm_stats after a two-pass RHS: the WENO-AO pairs are the indicator's
+    flags; the limited cells are those whose states the oracle's limiter changes."""
+    say("case stats")
+    d, R, n = 2, 3, (32, 32)
+    U = inputs.cell_averages(inputs.discontinuous(9, d, 6, 100.0, 1000.0), 32, 1.4, rule="midpoint", q=4)
+    dev = K.KFVM(d, n, order=7)
+    assert dev.stats()["limiter_cells"] == 0                  # nothing reconstructed yet
+    dev.set_limiter(True, 0.1)
+    dev.set_indicator("kxrcf", M)
+    dev.rhs(U.cuda())
+    st = dev.stats()
+    fl = dev.get_flags().cpu().numpy()
+    assert st["weno_cell_vars"] == int(fl.astype(np.int64).sum())
+    orc = oracle_mod.Oracle(d, R, n, kappa=0.1, kxrcf_m=M)
+    free = oracle_mod.Oracle(d, R, n, limiter=False, kxrcf_m=M)
+    changed = (np.abs(orc.states(U.numpy()) - free.states(U.numpy())) > 0).any(axis=(1, 2))
+    say(f"  limited cells {st['limiter_cells']} (oracle {int(changed.sum())}), WENO pairs {st['weno_cell_vars']}")
+    assert changed.sum() > 0
+    assert abs(st["limiter_cells"] - int(changed.sum())) <= 2 + 0.01 * changed.sum()
+    dev.set_indicator(None)
+    dev.rhs(U.cuda())
+    assert dev.stats()["weno_cell_vars"] == 4 * 32 * 32
