@@ -82,6 +82,9 @@ def _load():
         _lib.oracle_kxrcf.restype = C.c_int
         _lib.oracle_kxrcf_cells.argtypes = [P(_Ctx), P(C.c_double), C.c_long, P(C.c_long), P(C.c_double)]
         _lib.oracle_kxrcf_cells.restype = C.c_int
+        _lib.oracle_step_ssp432.argtypes = [P(_Ctx), P(C.c_double), C.c_double, C.c_double, C.c_double,
+                                            P(C.c_double), P(C.c_double)]
+        _lib.oracle_step_ssp432.restype = C.c_int
     return _lib
 
 
@@ -237,6 +240,15 @@ class Oracle:
         U = self._check_U(U).copy()
         self._call(self._lib.oracle_step(C.byref(self._ctx), _ptr(U), float(dt)))
         return U
+
+    def step_ssp432(self, U, dt, atol=1e-6, rtol=1e-6):
+        """One SSP(4,3,2) step: (U+, weighted RMS norm of the embedded error estimate)."""
+        U = self._check_U(U)
+        out = np.empty_like(U)
+        err = C.c_double()
+        self._call(self._lib.oracle_step_ssp432(C.byref(self._ctx), _ptr(U), float(dt), float(atol), float(rtol),
+                                                _ptr(out), C.byref(err)))
+        return out, err.value
 
     def cfl_dt(self, U, cfl):
         U = self._check_U(U)

@@ -717,6 +717,55 @@ int oracle_step(const oracle_ctx *c, double *U, double dt)
     return err;
 }
 
+/* One step of SSP(4,3,2): the four-stage third-order strong-stability-preserving
+ * Runge-Kutta method of Kraaijevanger with the embedded three-stage second-order
+ * SSP method (section 6).  In Shu-Osher form with h = dt / 2:
+ *   U1 = U + h L(U),  U2 = U1 + h L(U1),  U3 = 2/3 U + 1/3 (U2 + h L(U2)),
+ *   U+ = U3 + h L(U3).
+ * The embedded method shares the first three stages: Uhat = 1/3 U + 2/3 (U2 +
+ * h L(U2)) = 2 U3 - U.  err_norm is the root mean square over every (variable,
+ * cell) of (U+ - Uhat) / (atol + rtol max(|U|, |U+|)).  U is kept; U_out
+ * receives U+. */
+int oracle_step_ssp432(const oracle_ctx *c, const double *U, double dt, double atol, double rtol, double *U_out,
+                       double *err_norm)
+{
+    long M = ncells(c) * c->nvar;
+    double h = 0.5 * dt;
+    double *L = (double *)malloc(sizeof(double) * M);
+    double *U1 = (double *)malloc(sizeof(double) * M);
+    double *U2 = (double *)malloc(sizeof(double) * M);
+    double *U3 = (double *)malloc(sizeof(double) * M);
+    int err = oracle_rhs(c, U, L);
+    if (err == OK) {
+        for (long i = 0; i < M; ++i) U1[i] = U[i] + h * L[i];
+        err = oracle_rhs(c, U1, L);
+    }
+    if (err == OK) {
+        for (long i = 0; i < M; ++i) U2[i] = U1[i] + h * L[i];
+        err = oracle_rhs(c, U2, L);
+    }
+    if (err == OK) {
+        for (long i = 0; i < M; ++i) U3[i] = 2.0 / 3.0 * U[i] + 1.0 / 3.0 * (U2[i] + h * L[i]);
+        err = oracle_rhs(c, U3, L);
+    }
+    if (err == OK) {
+        double acc = 0.0;
+        for (long i = 0; i < M; ++i) {
+            U_out[i] = U3[i] + h * L[i];
+            double uhat = 2.0 * U3[i] - U[i];
+            double sc = atol + rtol * fmax(fabs(U[i]), fabs(U_out[i]));
+            double e = (U_out[i] - uhat) / sc;
+            acc += e * e;
+        }
+        *err_norm = sqrt(acc / (double)M);
+    }
+    free(L);
+    free(U1);
+    free(U2);
+    free(U3);
+    return err;
+}
+
 /* dt = cfl / max_cell sum_a (|u_a| + c_s) / dx_a */
 int oracle_cfl_dt(const oracle_ctx *c, const double *U, double cfl, double *dt)
 {
