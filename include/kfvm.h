@@ -124,6 +124,21 @@ int kfvm_rhs(kfvm_ctx *ctx, const double *U, double *dUdt);
  * kfvm_set_checking). */
 int kfvm_step(kfvm_ctx *ctx, double *U, double dt);
 
+/* One step of SSP(4,3,2) (section 6): the four-stage third-order SSP Runge-Kutta
+ * method of Kraaijevanger, with h = dt / 2,
+ *   U1 = U + h L(U),  U2 = U1 + h L(U1),  U3 = 2/3 U + 1/3 (U2 + h L(U2)),
+ *   U_out = U3 + h L(U3),
+ * and the embedded three-stage second-order SSP method, which shares the first
+ * stages: Uhat = 1/3 U + 2/3 (U2 + h L(U2)) = 2 U3 - U.  *err_host (host memory)
+ * receives the root mean square over every (variable, cell) of
+ * (U_out - Uhat) / (atol + rtol max(|U|, |U_out|)), for error-based step-size
+ * control by the caller (accept when it is at most one).  U is not modified;
+ * U and U_out are distinct device buffers of nvar * ncells float64.
+ * Synchronising; returns KFVM_ERR_NONPHYSICAL if a stage met a non-physical
+ * state.  atol, rtol >= 0 with atol + rtol > 0. */
+int kfvm_step_ssp432(kfvm_ctx *ctx, const double *U, double *U_out, double dt, double atol, double rtol,
+                     double *err_host);
+
 /* dt = cfl / max_cells sum_a (|u_a| + c_s) / dx_a.  Synchronising; the result is
  * written to host memory. */
 int kfvm_cfl_dt(kfvm_ctx *ctx, const double *U, double cfl, double *dt_host);

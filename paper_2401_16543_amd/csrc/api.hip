@@ -515,6 +515,28 @@ int kfvm_step(kfvm_ctx *c, double *U, double dt)
     return rc;
 }
 
+int kfvm_step_ssp432(kfvm_ctx *c, const double *U, double *U_out, double dt, double atol, double rtol,
+                     double *err_host)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !U_out || !err_host) return fail(c, KFVM_ERR_ARG, "null pointer");
+    if (U == U_out) return fail(c, KFVM_ERR_ARG, "U and U_out must not alias");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, KFVM_ERR_ARG, "dt must be positive and finite");
+    if (!(atol >= 0.0) || !(rtol >= 0.0) || !(atol + rtol > 0.0)) return fail(c, KFVM_ERR_ARG, "bad tolerances");
+    const double h = 0.5 * dt;
+    double *S0 = c->work.stage[0], *S1 = c->work.stage[1];
+    int rc = stage_call(c, U, U, S0, 1, h);                      // U1 = U + h L(U)
+    if (rc == KFVM_OK) rc = stage_call(c, U, S0, S1, 1, h);      // U2 = U1 + h L(U1)
+    if (rc == KFVM_OK) rc = stage_call(c, U, S1, S0, 4, h);      // U3 = 2/3 U + 1/3 (U2 + h L(U2))
+    if (rc == KFVM_OK) rc = stage_call(c, U, S0, U_out, 1, h);   // U+ = U3 + h L(U3)
+    if (rc != KFVM_OK) return rc;
+    hipError_t e = kfvm::launch_ssp_error(U, S0, U_out, c->geom.ncell * c->nvar, atol, rtol, c->work.cfl_part,
+                                          c->d_dt, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    HIP_TRY(c, hipMemcpyAsync(err_host, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return sync_check(c);
+}
+
 int kfvm_cfl_dt(kfvm_ctx *c, const double *U, double cfl, double *dt_host)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");

@@ -70,7 +70,8 @@ struct Timing {
 };
 
 // Launchers, one per (dim, R); all asynchronous on `s`.
-// stage: 0 -> out = L(Uin); 1, 2, 3 -> the SSP-RK3 stage combinations with U0.
+// stage: 0 -> out = L(Uin); 1, 2, 3 -> the SSP-RK3 stage combinations with U0
+// (1 is also Uin + dt L(Uin) of SSP(4,3)); 4 -> 2/3 U0 + 1/3 (Uin + dt L(Uin)).
 hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const Work &w, const Limiter &lim,
                            int riemann, const double *U0, const double *Uin, double *out, int stage, double dt,
                            hipStream_t s, const Timing &tm);
@@ -100,6 +101,10 @@ hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, co
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s);
+// SSP(4,3,2): *out = root mean square over M values of (Up - (2 U3 - U)) /
+// (atol + rtol max(|U|, |Up|)); part: at least 1024 doubles of scratch.
+hipError_t launch_ssp_error(const double *U, const double *U3, const double *Up, long M, double atol, double rtol,
+                            double *part, double *out, hipStream_t s);
 // counts[0] += cells with a limiter factor below one (theta[2][ncell]);
 // counts[1] += nonzero bytes of flags[nvar][ncell] (skipped when flags is null)
 hipError_t launch_count_stats(const double *theta, const uint8_t *flags, long ncell, int nvar,

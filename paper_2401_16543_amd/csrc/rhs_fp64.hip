@@ -575,7 +575,8 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar,
         if (stage == 0) r = acc;
         else if (stage == 1) r = Uin[i] + dt * acc;
         else if (stage == 2) r = 0.75 * U0[i] + 0.25 * (Uin[i] + dt * acc);
-        else r = U0[i] / 3.0 + 2.0 / 3.0 * (Uin[i] + dt * acc);
+        else if (stage == 3) r = U0[i] / 3.0 + 2.0 / 3.0 * (Uin[i] + dt * acc);
+        else r = 2.0 / 3.0 * U0[i] + 1.0 / 3.0 * (Uin[i] + dt * acc);   // third stage of SSP(4,3)
         out[i] = r;
     }
 }
@@ -656,6 +657,46 @@ __global__ __launch_bounds__(256) void k_cfl_final(const double *__restrict__ pa
         for (int i = 1; i < 256 / 64; ++i) r = fmax(r, red[i]);
         *dt = cfl / r;
     }
+}
+
+// --------------------------------------------------- SSP(4,3,2) error norm ---
+// Sum over (variable, cell) of ((U+ - (2 U3 - U)) / (atol + rtol max(|U|, |U+|)))^2:
+// per-block partial sums in a fixed order (grid-stride, then a tree in LDS),
+// then one block adds the partials, so the norm does not depend on timing.
+__global__ __launch_bounds__(256) void k_err_partial(const double *__restrict__ U, const double *__restrict__ U3,
+                                                     const double *__restrict__ Up, long M, double atol, double rtol,
+                                                     double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x) {
+        const double uhat = 2.0 * U3[i] - U[i];
+        const double sc = atol + rtol * fmax(fabs(U[i]), fabs(Up[i]));
+        const double e = (Up[i] - uhat) / sc;
+        acc += e * e;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_err_final(const double *__restrict__ part, int nparts, long M,
+                                                   double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0] / (double)M);
 }
 
 // ------------------------------------------------------------ statistics ---
@@ -755,6 +796,15 @@ hipError_t launch_recon_ratio(int dim, int R, const Geom &g, const Tables &t, co
     if (dim == 3 && R == 2) return ratio_impl<3, 2>(g, t, w, lim, U, ratio, s);
     if (dim == 3 && R == 3) return ratio_impl<3, 3>(g, t, w, lim, U, ratio, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_ssp_error(const double *U, const double *U3, const double *Up, long M, double atol, double rtol,
+                            double *part, double *out, hipStream_t s)
+{
+    const int nb = (int)std::min<long>((M + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_err_partial, dim3((unsigned)nb), dim3(256), 0, s, U, U3, Up, M, atol, rtol, part);
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, s, part, nb, M, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_count_stats(const double *theta, const uint8_t *flags, long ncell, int nvar,

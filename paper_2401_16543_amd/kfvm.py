@@ -23,7 +23,7 @@ EXPORTED = [
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
     "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step", "kfvm_set_indicator", "kfvm_kxrcf",
-    "kfvm_set_boundary",
+    "kfvm_set_boundary", "kfvm_step_ssp432",
 ]
 KERNEL_CLASSES = ("recon", "flux", "update", "indicator")
 KFVM_IND_NONE, KFVM_IND_KXRCF = 0, 1
@@ -90,6 +90,7 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_kernel_times": ([vp, dp, C.POINTER(C.c_longlong), ip], ip),
         "kfvm_set_indicator": ([vp, ip, C.c_double], ip),
         "kfvm_set_boundary": ([vp, ip, ip, ip, dp, dp], ip),
+        "kfvm_step_ssp432": ([vp, vp, vp, C.c_double, C.c_double, C.c_double, dp], ip),
         "kfvm_kxrcf": ([vp, vp, C.c_double, vp, vp], ip),
         "kfvm_destroy": ([vp], None),
     }
@@ -204,6 +205,15 @@ class KFVM:
         self._stream()
         self._check(self.lib.kfvm_step(self._h, self._state(U), float(dt)))
         return U
+
+    def step_ssp432(self, U, U_out, dt: float, atol: float = 1e-6, rtol: float = 1e-6) -> float:
+        """One SSP(4,3,2) step from U into U_out; returns the weighted RMS norm of the
+        embedded error estimate (accept the step when it is at most one)."""
+        self._stream()
+        err = C.c_double()
+        self._check(self.lib.kfvm_step_ssp432(self._h, self._state(U), self._state(U_out), float(dt), float(atol),
+                                              float(rtol), C.byref(err)))
+        return err.value
 
     def cfl_dt(self, U, cfl: float) -> float:
         self._stream()
