@@ -45,7 +45,7 @@ class _Ctx(C.Structure):
         ("gl_w", C.POINTER(C.c_double)), ("eps", C.c_double),
         ("limiter", C.c_int), ("kappa", C.c_double), ("riemann", C.c_int),
         ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)), ("kxrcf_m", C.c_double),
-        ("bc", C.c_int * 6), ("bc_state", C.c_double * 30),
+        ("bc", C.c_int * 6), ("bc_state", C.c_double * 30), ("flat_k1", C.c_double),
     ]
 
 BC_KINDS = {"periodic": 0, "outflow": 1, "reflecting": 2, "inflow": 3}
@@ -85,6 +85,8 @@ def _load():
         _lib.oracle_step_ssp432.argtypes = [P(_Ctx), P(C.c_double), C.c_double, C.c_double, C.c_double,
                                             P(C.c_double), P(C.c_double)]
         _lib.oracle_step_ssp432.restype = C.c_int
+        _lib.oracle_flattener.argtypes = [P(_Ctx), P(C.c_double), P(C.c_double)]
+        _lib.oracle_flattener.restype = C.c_int
     return _lib
 
 
@@ -101,7 +103,7 @@ class Oracle:
 
     def __init__(self, d: int, R: int, n, dx=None, gamma: float = 1.4, *, limiter: bool = True,
                  kappa: float = 0.5, riemann: str = "hllc", weno: bool = True, tables=None,
-                 kxrcf_m: float | None = None):
+                 kxrcf_m: float | None = None, flattener: float | None = None):
         self.d, self.R = d, R
         self.nvar = d + 2
         n = list(n) + [1] * (3 - len(n))
@@ -145,6 +147,7 @@ class Oracle:
         ctx.weno = int(weno)
         ctx.flags = C.POINTER(C.c_uint8)()
         ctx.kxrcf_m = float(kxrcf_m) if kxrcf_m else 0.0
+        ctx.flat_k1 = float(flattener) if flattener else 0.0
         self._ctx = ctx
         self._lib = _load()
 
@@ -173,6 +176,18 @@ class Oracle:
                     raise ValueError("an inflow side needs its conserved state")
                 for v in range(self.nvar):
                     self._ctx.bc_state[(2 * axis + side) * 5 + v] = float(st[v])
+
+    def set_flattener(self, k1):
+        """The limiter's flattener eta (section 4; the compression ramp with onset
+        k1, see oracle_flattener) instead of eta = 0 (None or 0: off)."""
+        self._ctx.flat_k1 = float(k1) if k1 else 0.0
+
+    def flattener(self, U):
+        """eta of every cell [cells] (0 with the flattener off)."""
+        U = self._check_U(U)
+        eta = np.empty(self.ncell)
+        self._call(self._lib.oracle_flattener(C.byref(self._ctx), _ptr(U), _ptr(eta)))
+        return eta
 
     def set_kxrcf(self, m):
         """The KXRCF indicator (section 3.5) with threshold Delta^m picks the WENO

@@ -22,7 +22,8 @@
  *      (eq. recVarToCons, eq. lpToConsMat);
  *   3. the positivity limiter of section 4 (density scaling eq. ppThetaRho and
  *      eq. ppCorrectDens, pressure scaling by bisection eq. thetapRoot, eq. thetaP
- *      and eq. ppCorrectPres), with the flattener eta = 0 and kappa a parameter;
+ *      and eq. ppCorrectPres), with kappa a parameter and the flattener eta
+ *      either 0 or the compression ramp of flattener() below;
  *   4. Riemann states outside the domain from the inner ones at boundary
  *      faces (ghost_face_states);
  *   5. an approximate Riemann solver at every face Gauss point: HLLC (Toro,
@@ -76,6 +77,7 @@ typedef struct {
     double kxrcf_m;        /* > 0: the KXRCF indicator with threshold Delta^m picks the WENO cells */
     int bc[3][2];          /* boundary condition per axis and side (lower, upper): BC_* below */
     double bc_state[3][2][MAXV];   /* conserved inflow state per axis and side */
+    double flat_k1;        /* > 0: the flattener eta of the limiter bounds (flattener()); 0: eta = 0 */
 } oracle_ctx;
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTING = 2, BC_INFLOW = 3 };
@@ -180,6 +182,49 @@ static int admissible(const oracle_ctx *c, const double *u)
     for (int v = 0; v < c->nvar; ++v)
         if (!isfinite(u[v])) return 0;
     return u[0] > 0.0 && pressure(c, u) > 0.0;
+}
+
+/* ----------------------------------------------------------- flattener --- */
+/* The flattener eta of the limiter bounds (section 4).  The paper takes kappa
+ * and eta from a rule it cites but does not state; this is a reading: eta
+ * rises from 0 to 1 with the compression of the flow at the cell, measured by
+ * the undivided velocity divergence
+ *     d = sum_a (v_a(c + e_a) - v_a(c - e_a)) / 2
+ * (neighbours through the ghost fill) against the least sound speed c_min of
+ * the 3^d block:
+ *     eta = min(1, max(0, -d / (k1 c_min) - 1)),
+ * so eta = 0 wherever d >= -k1 c_min (expansion, uniform or mildly compressed
+ * flow: the bounds keep their kappa widening) and eta = 1 wherever
+ * d <= -2 k1 c_min (strong compression: the bounds are the neighbourhood's own
+ * extrema).  k1 = flat_k1; without it eta = 0.  Every state of the block must be
+ * admissible (the caller has checked). */
+static double flattener(const oracle_ctx *c, const double *U, long cell)
+{
+    if (!(c->flat_k1 > 0.0)) return 0.0;
+    double d = 0.0;
+    for (int a = 0; a < c->dim; ++a) {
+        int op[3] = {0, 0, 0}, om[3] = {0, 0, 0};
+        op[a] = 1;
+        om[a] = -1;
+        double up[MAXV], um[MAXV];
+        neighbor_state(c, U, cell, op, up);
+        neighbor_state(c, U, cell, om, um);
+        d += 0.5 * (up[1 + a] / up[0] - um[1 + a] / um[0]);
+    }
+    double cmin = INFINITY;
+    int lo[3] = {-1, -1, -1}, hi[3] = {1, 1, 1};
+    if (c->dim < 3) lo[2] = hi[2] = 0;
+    for (int dz = lo[2]; dz <= hi[2]; ++dz)
+        for (int dy = lo[1]; dy <= hi[1]; ++dy)
+            for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+                int off[3] = {dx, dy, dz};
+                double un[MAXV];
+                neighbor_state(c, U, cell, off, un);
+                double cs = sqrt(c->gamma * pressure(c, un) / un[0]);
+                if (cs < cmin) cmin = cs;
+            }
+    double eta = -d / (c->flat_k1 * cmin) - 1.0;
+    return eta < 0.0 ? 0.0 : (eta > 1.0 ? 1.0 : eta);
 }
 
 /* ----------------------------------------- linearised primitive variables --- */
@@ -323,10 +368,13 @@ static int cell_states_ex(const oracle_ctx *c, const double *U, long cell, doubl
                 if (un[0] < rmin) rmin = un[0];
                 if (pn < pmin) pmin = pn;
             }
-    /* widened bounds with the flattener eta = 0 */
-    rmax *= 1.0 + c->kappa;
-    rmin *= 1.0 - c->kappa;
-    pmin *= 1.0 - c->kappa;
+    /* bounds widened by kappa (1 - eta): rho_max (1 + kappa - kappa eta),
+     * rho_min (1 - kappa + kappa eta), p_min (1 - kappa + kappa eta) */
+    double eta = flattener(c, U, cell);
+    double f = c->kappa * (1.0 - eta);
+    rmax *= 1.0 + f;
+    rmin *= 1.0 - f;
+    pmin *= 1.0 - f;
 
     /* density scaling (eq. ppThetaRho): only the violated side of each bound */
     double th = 1.0;
@@ -558,6 +606,31 @@ int oracle_kxrcf_cells(const oracle_ctx *c, const double *U, long count, const l
 #pragma omp parallel for schedule(dynamic, 1)
     for (long i = 0; i < count; ++i) measure[i] = kxrcf_measure(c, U, cells[i], NULL);
     return OK;
+}
+
+/* The flattener eta of every cell (0 where the limiter's neighbourhood holds a
+ * state that is not admissible).  eta: [cells]. */
+int oracle_flattener(const oracle_ctx *c, const double *U, double *eta)
+{
+    long N = ncells(c);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long cell = 0; cell < N; ++cell) {
+        int ok = 1;
+        int lo[3] = {-1, -1, -1}, hi[3] = {1, 1, 1};
+        if (c->dim < 3) lo[2] = hi[2] = 0;
+        for (int dz = lo[2]; dz <= hi[2]; ++dz)
+            for (int dy = lo[1]; dy <= hi[1]; ++dy)
+                for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+                    int off[3] = {dx, dy, dz};
+                    double un[MAXV];
+                    neighbor_state(c, U, cell, off, un);
+                    ok = ok && admissible(c, un);
+                }
+        eta[cell] = ok ? flattener(c, U, cell) : 0.0;
+        bad |= !ok;
+    }
+    return bad ? ERR_NONPHYSICAL : OK;
 }
 
 /* ----------------------------------------------------------- exported --- */
