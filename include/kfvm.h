@@ -176,9 +176,22 @@ int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 int kfvm_set_boundary(kfvm_ctx *ctx, int axis, int lower, int upper, const double *lower_state,
                       const double *upper_state);
 
-/* Positivity limiter of section 4 with flattener eta = 0: enabled != 0 turns it
- * on; bounds are widened by the factor (1 +- kappa), 0 <= kappa < 1. */
+/* Positivity limiter of section 4: enabled != 0 turns it on; the bounds are
+ * the 3^d neighbourhood's extrema widened by the factor (1 +- kappa (1 - eta)),
+ * 0 <= kappa < 1, with the flattener eta = 0 unless kfvm_set_flattener turns
+ * it on. */
 int kfvm_set_limiter(kfvm_ctx *ctx, int enabled, double kappa);
+
+/* The limiter's flattener eta (section 4: rho_max (1 + kappa - kappa eta),
+ * rho_min and p_min (1 - kappa + kappa eta), eta tending to one where the flow
+ * compresses).  The paper takes eta's rule from a cited reference; this library
+ * reads it as a ramp in the undivided velocity divergence
+ * d = sum_a (v_a(c + e_a) - v_a(c - e_a)) / 2 (neighbours through the ghost
+ * fill) against the least sound speed c_min of the cell's 3^d block:
+ * eta = min(1, max(0, -d / (k1 c_min) - 1)).  k1 > 0 turns it on with that
+ * onset; k1 = 0 (the default) gives eta = 0.  Every precision mode supports it.
+ * Errors: KFVM_ERR_ARG (k1 negative or not finite). */
+int kfvm_set_flattener(kfvm_ctx *ctx, double k1);
 
 /* KFVM_HLLC (default) or KFVM_HLL (section 6). */
 int kfvm_set_riemann(kfvm_ctx *ctx, int solver);

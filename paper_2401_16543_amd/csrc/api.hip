@@ -16,7 +16,7 @@
 struct kfvm_ctx {
     int dim = 0, R = 0, nvar = 0;
     kfvm::Geom geom{};
-    kfvm::Limiter lim{1, 0.5};
+    kfvm::Limiter lim{1, 0.5, 0.0};
     int riemann = KFVM_HLLC;
     int precision = KFVM_FP64;
     int checking = 0;
@@ -576,6 +576,14 @@ int kfvm_set_limiter(kfvm_ctx *c, int enabled, double kappa)
     if (!(kappa >= 0.0 && kappa < 1.0)) return fail(c, KFVM_ERR_ARG, "kappa must lie in [0, 1)");
     c->lim.on = enabled != 0;
     c->lim.kappa = kappa;
+    return KFVM_OK;
+}
+
+int kfvm_set_flattener(kfvm_ctx *c, double k1)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!(k1 >= 0.0 && k1 < INFINITY)) return fail(c, KFVM_ERR_ARG, "the flattener onset k1 must be finite and >= 0");
+    c->lim.flat_k1 = k1;
     return KFVM_OK;
 }
 

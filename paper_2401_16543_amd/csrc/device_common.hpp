@@ -365,6 +365,33 @@ __device__ __forceinline__ double face_weight(int gi)
 }
 
 
+// Flattener of the positivity limiter's bounds (section 4: rho_max (1 + kappa -
+// kappa eta), rho_min and p_min (1 - kappa + kappa eta)).  The paper takes eta
+// from a cited rule it does not state; here eta rises from 0 to 1 with the
+// compression at the cell: d is the undivided velocity divergence
+// sum_a (v_a(c + e_a) - v_a(c - e_a)) / 2 and c2min the least squared sound
+// speed gamma p / rho of the 3^d block, and
+//   eta = min(1, max(0, -d / (k1 c_min) - 1)),
+// zero down to d = -k1 c_min, one from d = -2 k1 c_min.
+__device__ __forceinline__ double flattener_eta(double d, double c2min, double k1)
+{
+    const double e = -d / (k1 * sqrt(c2min)) - 1.0;
+    return fmin(1.0, fmax(0.0, e));
+}
+
+// undivided velocity divergence at tile cell lc (strides 1, sy, sz of the axes)
+template <int D, typename T>
+__device__ __forceinline__ double undivided_divergence(const T &tile, int lc, int sy, int sz)
+{
+    double d = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int s = a == 0 ? 1 : (a == 1 ? sy : sz);
+        d += 0.5 * (tile[1 + a][lc + s] / tile[0][lc + s] - tile[1 + a][lc - s] / tile[0][lc - s]);
+    }
+    return d;
+}
+
 // GELU, tanh form (Hendrycks & Gimpel 2016), float32: 0.5 z (1 + tanh a) with
 // a = sqrt(2/pi) (z + 0.044715 z^3) equals z / (1 + 2^(-2 a log2 e)), taken with
 // the hardware base-2 exponential and reciprocal

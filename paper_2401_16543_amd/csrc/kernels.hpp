@@ -22,6 +22,7 @@ struct Geom {
 struct Limiter {
     int on;
     double kappa;
+    double flat_k1;     // > 0: the flattener eta narrows the kappa widening (flattener_eta); 0: eta = 0
 };
 
 // Device buffers owned by a context.

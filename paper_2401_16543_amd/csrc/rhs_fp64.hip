@@ -360,7 +360,8 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
     // positivity limiter (section 4) on the cell's Riemann states
     double th_rho = 1.0, th_p = 1.0;
     if (lim.on) {
-        double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+        double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY, c2min = INFINITY;
+        const bool flat = lim.flat_k1 > 0.0;
         bool ok = true;
 #pragma unroll 1
         for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
@@ -377,11 +378,17 @@ __global__ __launch_bounds__((Cfg<D, R>::NT)) void k_recon(const double *__restr
                     rmax = fmax(rmax, un[0]);
                     rmin = fmin(rmin, un[0]);
                     pmin = fmin(pmin, pn);
+                    if (flat) c2min = fmin(c2min, gam * pn / un[0]);
                 }
         if (!ok) *err = ERR_NONPHYSICAL;
-        rmax *= 1.0 + lim.kappa;
-        rmin *= 1.0 - lim.kappa;
-        pmin *= 1.0 - lim.kappa;
+        // bounds widened by kappa (1 - eta)
+        const double f =
+            flat ? lim.kappa * (1.0 - flattener_eta(undivided_divergence<D>(tile, lc, C::HX, C::HX * C::HY), c2min,
+                                                    lim.flat_k1))
+                 : lim.kappa;
+        rmax *= 1.0 + f;
+        rmin *= 1.0 - f;
+        pmin *= 1.0 - f;
         PhiInv<D> pi;
         pi.init(ref, gam);
         // density scaling (eq. ppThetaRho), only the violated side of each bound;

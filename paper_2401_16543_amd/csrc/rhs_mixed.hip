@@ -561,7 +561,8 @@ __device__ __forceinline__ void limiter_factors(const double (*tile)[MCfg<D, R>:
     th_rho = 1.0;
     th_p = 1.0;
     // bounds over the 3^d block; the two half-waves take alternate neighbours
-    double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY;
+    double rmax = -INFINITY, rmin = INFINITY, pmin = INFINITY, c2min = INFINITY;
+    const bool flat = lim.flat_k1 > 0.0;
     constexpr int NB = D == 3 ? 27 : 9;
 #pragma unroll
     for (int j = 0; j < (NB + 1) / 2; ++j) {
@@ -573,14 +574,22 @@ __device__ __forceinline__ void limiter_factors(const double (*tile)[MCfg<D, R>:
         rmax = fmax(rmax, r);
         rmin = fmin(rmin, r);
         pmin = fmin(pmin, (double)ptile[o]);
+        if (flat) c2min = fmin(c2min, gam * (double)ptile[o] / r);
     }
     rmax = pair_max(rmax);
     rmin = pair_min(rmin);
     pmin = pair_min(pmin);
     if (!(pmin > 0.0) && active) *err = ERR_NONPHYSICAL;   // a neighbour is not admissible
-    rmax *= 1.0 + lim.kappa;
-    rmin *= 1.0 - lim.kappa;
-    pmin *= 1.0 - lim.kappa;
+    // bounds widened by kappa (1 - eta)
+    double f = lim.kappa;
+    if (flat) {
+        c2min = pair_min(c2min);
+        f = lim.kappa * (1.0 - flattener_eta(undivided_divergence<D>(tile, lc, C::HX, C::HX * C::HY), c2min,
+                                             lim.flat_k1));
+    }
+    rmax *= 1.0 + f;
+    rmin *= 1.0 - f;
+    pmin *= 1.0 - f;
     bool exact = false;
     if (active && ok) {
         // density scaling (eq. ppThetaRho) from the extreme point values: the
