@@ -11,9 +11,10 @@ from __future__ import annotations
 
 
 def integrate(dev, U, t_end: float, atol: float = 1e-6, rtol: float = 1e-6, cfl_max: float = 1.0,
-              dt0: float | None = None, max_steps: int = 10 ** 7) -> dict:
+              dt0: float | None = None, max_steps: int = 10 ** 7, on_step=None) -> dict:
     """Advance U (a device tensor, updated in place) from 0 to t_end.  Returns the
-    counts of accepted and rejected steps and of right-hand-side evaluations."""
+    counts of accepted and rejected steps and of right-hand-side evaluations.
+    on_step(t, accepted, rejected), if given, is called after every attempt."""
     import torch
     out = torch.empty_like(U)
     t, accepted, rejected = 0.0, 0, 0
@@ -27,6 +28,8 @@ def integrate(dev, U, t_end: float, atol: float = 1e-6, rtol: float = 1e-6, cfl_
             accepted += 1
         else:
             rejected += 1
+        if on_step is not None:
+            on_step(t, accepted, rejected)
         fac = 5.0 if err == 0.0 else min(5.0, max(0.2, 0.9 * err ** (-1.0 / 3.0)))
         dt *= fac
     return {"t": t, "accepted": accepted, "rejected": rejected, "rhs_evaluations": 4 * (accepted + rejected)}

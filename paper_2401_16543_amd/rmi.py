@@ -1,17 +1,19 @@
 """The Richtmyer-Meshkov run of section 6.3 on one GPU through the library.
 
     python -m paper_2401_16543_amd.rmi [--R 2] [--cells-per-unit 512] [--t-end 3.33]
-                                       [--cfl 0.5] [--no-indicator] [--precision fp64]
-                                       [--compare-fp64]
+                                       [--integrator ssp3|ssp432] [--cfl 0.5]
+                                       [--tol 1e-3] [--no-indicator] [--flattener K1]
+                                       [--precision fp64] [--compare-fp64]
 
 Domain [-1/2, 11/2] x [0, 1] at spacing 1/512 (3072 x 512 cells), Mach-3 shock
 into an oblique density jump (rho_D = 2), fixed inflow at x = -1/2, outflow at
-x = 11/2, reflecting walls in y; any precision path, SSP-RK3 at a fixed CFL number
-(the paper integrates with its adaptive SSP(4,3,2)), with or without the KXRCF
-two-pass reconstruction (m = 3/2).  Prints a progress line every few hundred
-steps and one JSON summary: right-hand-side evaluations, wall time per
-evaluation, device time per kernel class, and the fraction of cells the
-indicator flags at the end.
+x = 11/2, reflecting walls in y; any precision path, with or without the KXRCF
+two-pass reconstruction (m = 3/2) and the limiter's flattener.  Time stepping:
+SSP-RK3 at a fixed CFL number, or the paper's choice for this run, SSP(4,3,2)
+with error-based step control (atol = rtol = 1e-3, CFL at most 1).  Prints a
+progress line every few hundred steps and one JSON summary: right-hand-side
+evaluations, wall time per evaluation, device time per kernel class, and the
+fraction of cells the indicator flags at the end.
 """
 from __future__ import annotations
 
@@ -23,9 +25,11 @@ import time
 
 def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float = 0.5, indicator: bool = True,
         report_every: int = 500, max_steps: int | None = None, precision: str = "fp64", keep_state: bool = False,
-        dts=None) -> dict:
-    """One run; `dts` replays a recorded sequence of step sizes (the summary's
-    "dts" when keep_state is set) so that two runs can be compared state for state."""
+        dts=None, integrator: str = "ssp3", tol: float = 1e-3, flattener: float | None = None) -> dict:
+    """One run; `dts` replays a recorded sequence of SSP-RK3 step sizes (the
+    summary's "dts" when keep_state is set) so that two runs can be compared state
+    for state.  integrator "ssp432" takes atol = rtol = tol and cfl as the
+    largest CFL number."""
     import torch
 
     from . import inputs, kfvm
@@ -38,6 +42,8 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
     dev.set_precision(precision)
     if indicator:
         dev.set_indicator("kxrcf", 1.5)
+    if flattener:
+        dev.set_flattener(flattener)
     dev.set_timing(True)
     dev.kernel_times()
     torch.cuda.synchronize()
@@ -51,7 +57,19 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
 
     taken = []
     t0 = time.perf_counter()
-    while t < t_end - 1e-12 and (max_steps is None or steps < max_steps):
+    if integrator == "ssp432":
+        from .integrate import integrate
+
+        def on_step(tt, acc, rej):
+            if (acc + rej) % report_every == 0:
+                collect()
+                print(f"# attempt {acc + rej} ({rej} rejected) t={tt:.4f} wall {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+
+        res = integrate(dev, U, t_end, atol=tol, rtol=tol, cfl_max=cfl,
+                        max_steps=max_steps if max_steps is not None else 10 ** 7, on_step=on_step)
+        t, steps = res["t"], res["accepted"] + res["rejected"]
+    while integrator == "ssp3" and t < t_end - 1e-12 and (max_steps is None or steps < max_steps):
         if dts is not None:
             if steps >= len(dts):
                 break
@@ -70,14 +88,16 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
     status = dev.status()
     collect()
     flagged = float(dev.get_flags()[0].float().mean()) if indicator else 1.0
-    nrhs = 3 * steps
+    nrhs = (4 if integrator == "ssp432" else 3) * steps
     out = {"problem": "Richtmyer-Meshkov, Ma 3, rho_D 2", "R": R, "grid": [nx, ny], "t": t, "steps": steps,
-            "precision": precision,
+            "precision": precision, "integrator": integrator, "flattener_k1": flattener,
             "rhs_evaluations": nrhs, "cfl": cfl, "indicator": "KXRCF m=3/2" if indicator else "none (WENO-AO everywhere)",
             "wall_s": wall, "wall_ms_per_rhs": wall / nrhs * 1e3,
             "device_ms_total": totals,
             "flagged_fraction_final": flagged, "status": status,
             "rho_range": [float(U[0].min()), float(U[0].max())]}
+    if integrator == "ssp432":
+        out.update(tol=tol, accepted=res["accepted"], rejected=res["rejected"])
     if keep_state:
         out["U"] = U
         out["dts"] = taken
@@ -89,18 +109,25 @@ def main():
     ap.add_argument("--R", type=int, default=2)
     ap.add_argument("--cells-per-unit", type=int, default=512)
     ap.add_argument("--t-end", type=float, default=3.33)
-    ap.add_argument("--cfl", type=float, default=0.5)
+    ap.add_argument("--integrator", default="ssp3", choices=["ssp3", "ssp432"])
+    ap.add_argument("--cfl", type=float, default=None, help="CFL number (ssp3, default 0.5) or its cap (ssp432, default 1)")
+    ap.add_argument("--tol", type=float, default=1e-3, help="ssp432: atol = rtol")
+    ap.add_argument("--flattener", type=float, default=None, help="the limiter flattener's onset k1 (default off)")
     ap.add_argument("--no-indicator", action="store_true")
     ap.add_argument("--max-steps", type=int, default=None)
     ap.add_argument("--precision", default="fp64", help="fp64, split_f16 or split_bf16")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also run the FP64 path with the same step sizes and report the L1 density difference")
     a = ap.parse_args()
-    out = run(a.R, a.cells_per_unit, a.t_end, a.cfl, not a.no_indicator, max_steps=a.max_steps,
-              precision=a.precision, keep_state=a.compare_fp64)
+    cfl = a.cfl if a.cfl is not None else (1.0 if a.integrator == "ssp432" else 0.5)
+    if a.compare_fp64 and a.integrator != "ssp3":
+        ap.error("--compare-fp64 replays SSP-RK3 step sizes: use --integrator ssp3")
+    out = run(a.R, a.cells_per_unit, a.t_end, cfl, not a.no_indicator, max_steps=a.max_steps,
+              precision=a.precision, keep_state=a.compare_fp64, integrator=a.integrator, tol=a.tol,
+              flattener=a.flattener)
     if a.compare_fp64:
-        ref = run(a.R, a.cells_per_unit, a.t_end, a.cfl, not a.no_indicator, precision="fp64", keep_state=True,
-                  dts=out["dts"])
+        ref = run(a.R, a.cells_per_unit, a.t_end, cfl, not a.no_indicator, precision="fp64", keep_state=True,
+                  dts=out["dts"], flattener=a.flattener)
         out["l1_rho_vs_fp64"] = float((out["U"][0] - ref["U"][0]).abs().mean())
         out["fp64_wall_ms_per_rhs"] = ref["wall_ms_per_rhs"]
         out.pop("U")
