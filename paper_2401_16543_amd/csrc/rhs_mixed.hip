@@ -216,6 +216,37 @@ __device__ __forceinline__ f16v unit_regs(const float *vec, int hf)
     return a;
 }
 
+// GELU of the inference by chords: bin k of width 1/64 on [-6, 6) holds
+// (a_k, b_k), the line through gelu_f at the bin's ends; below -6 and from 6 on
+// the end chords continue (GELU is 0 or z there to 1e-8).  The chords are
+// within 2.5e-5 of gelu_f, far below the BF16 rounding of the hidden layer, and
+// cost one LDS read and a few plain VALU operations against the exponential and
+// reciprocal of gelu_f, which the VALU-bound gated reconstruction feels.  The
+// table sits in LDS after the gate's vector parameters (GVEC_TAB floats on).
+constexpr int GELU_NB = 768;
+constexpr int GVEC_TAB = 104;                          // after b1, b2, w3, b3 (97 floats), 16-byte aligned
+constexpr int GVEC_SIZE = GVEC_TAB + 2 * GELU_NB;
+
+__device__ __forceinline__ void gelu_table_fill(float *gvec, int tid, int nt)
+{
+    float2 *tab = reinterpret_cast<float2 *>(gvec + GVEC_TAB);
+    for (int k = tid; k < GELU_NB; k += nt) {
+        const float z0 = -6.f + (float)k * (1.f / 64.f), z1 = z0 + 1.f / 64.f;
+        const float g0 = gelu_f(z0), g1 = gelu_f(z1);
+        const float b = (g1 - g0) * 64.f;
+        tab[k] = make_float2(g0 - b * z0, b);
+    }
+}
+
+__device__ __forceinline__ float gelu_tab(float z, const float *gvec)
+{
+    const float2 *tab = reinterpret_cast<const float2 *>(gvec + GVEC_TAB);
+    // bin index clamped in float (fmaxf of NaN gives 0, so it stays in range)
+    const int k = (int)fminf(fmaxf(fmaf(z, 64.f, 384.f), 0.f), (float)(GELU_NB - 1));
+    const float2 c = tab[k];
+    return fmaf(c.y, z, c.x);
+}
+
 // logit of this lane's cell (identical in both half-waves); xb: the lane's BF16
 // input operands.  Both layers start their accumulators from the biases.
 template <int D>
@@ -230,7 +261,7 @@ __device__ __forceinline__ float gate_forward(const uint4 (&xb)[GateShape<D>::KS
     uint32_t P[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-        P[p] = pack_bf16(gelu_f(acc[2 * p]), gelu_f(acc[2 * p + 1]));
+        P[p] = pack_bf16(gelu_tab(acc[2 * p], vec), gelu_tab(acc[2 * p + 1], vec));
         asm volatile("" : "+v"(P[p]));
     }
     // to the B layout (unit 16 ks + 8 hf + i): swap the pairs each half needs
@@ -247,7 +278,7 @@ __device__ __forceinline__ float gate_forward(const uint4 (&xb)[GateShape<D>::KS
     const f16v w3 = unit_regs(vec + 64, hf);
     float part = 0.f;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) part = fmaf(w3[j], gelu_f(acc2[j]), part);
+    for (int j = 0; j < 16; ++j) part = fmaf(w3[j], gelu_tab(acc2[j], vec), part);
     return pair_sum(part) + vec[96];
 }
 
@@ -650,7 +681,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     __shared__ uint4 As[M::A_FULL];
     __shared__ uint4 Al[M::A_LIN];
     __shared__ uint4 Wg[GATE ? GateShape<D>::SLOTS : 1];
-    __shared__ __align__(16) float gvec[GATE ? 100 : 4];
+    __shared__ __align__(16) float gvec[GATE ? GVEC_SIZE : 4];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
     const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
@@ -666,6 +697,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     if constexpr (GATE) {
         for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];
         for (int i = threadIdx.x; i < 97; i += M::NT) gvec[i] = ga.vec[i];
+        gelu_table_fill(gvec, threadIdx.x, M::NT);
     }
     __syncthreads();
 
@@ -770,7 +802,7 @@ __global__ __launch_bounds__((MixCfg<D, 2>::NT)) void k_gate_flags(const double 
     constexpr int NV = C::NV;
     __shared__ double tile[NV][C::HN];
     __shared__ uint4 Wg[GateShape<D>::SLOTS];
-    __shared__ __align__(16) float gvec[100];
+    __shared__ __align__(16) float gvec[GVEC_SIZE];
 
     const int nbx = (g.n[0] + C::TX - 1) / C::TX, nby = (g.n[1] + C::TY - 1) / C::TY;
     const int nbz = D == 3 ? (g.n[2] + C::TZ - 1) / C::TZ : 1;
@@ -784,6 +816,7 @@ __global__ __launch_bounds__((MixCfg<D, 2>::NT)) void k_gate_flags(const double 
                            (double *)nullptr);
     for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];
     for (int i = threadIdx.x; i < 97; i += M::NT) gvec[i] = ga.vec[i];
+    gelu_table_fill(gvec, threadIdx.x, M::NT);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;

@@ -5,9 +5,10 @@
   reduction on a synthetic task;
 * sample export: network inputs and omega_0 / gamma_0 against the oracle;
 * fused inference in the split-precision reconstruction: decisions against
-  the oracle network on the oracle's inputs (disagreements only where the logit
-  sits within float32 noise of the threshold), and the gated right-hand side
-  against the oracle replaying the same decisions.
+  the oracle network, with the inference's chord GELU, on the oracle's inputs
+  (disagreements only where the logit sits within float32 noise of the
+  threshold), and the gated right-hand side against the oracle replaying the
+  same decisions.
 """
 import numpy as np
 import pytest
@@ -117,7 +118,7 @@ def test_fused_gate_decisions_and_replay(K, oracle_mod, d, R, n):
     n_in, _ = dev.mlp_sizes()
     p = _params(n_in, 9, scale=2.0)
     x_ref = orc.gate_inputs(U.numpy()).reshape(-1, n_in)
-    z_ref = mlp.forward(p, x_ref, bf16=True)[0].reshape(d + 2, -1)
+    z_ref = mlp.forward(p, x_ref, bf16=True, chords=True)[0].reshape(d + 2, -1)
     # S0 increments at rounding level are smooth by definition; these fields have none
     flat = np.zeros((d + 2, x_ref.shape[0] // (d + 2)), dtype=bool)
     thr = float(np.median(z_ref))
@@ -201,7 +202,7 @@ def test_gate_dilated_for_3d_order7(K, oracle_mod):
     n_in, _ = dev.mlp_sizes()
     p = _params(n_in, 13, scale=2.0)
     x_ref = orc.gate_inputs(U.numpy()).reshape(-1, n_in)
-    z = mlp.forward(p, x_ref, bf16=True)[0].reshape(d + 2, n[2], n[1], n[0])
+    z = mlp.forward(p, x_ref, bf16=True, chords=True)[0].reshape(d + 2, n[2], n[1], n[0])
     thr = float(np.quantile(z, 0.85))
     near = np.abs(z - thr) <= 2e-3 * (1.0 + abs(thr))
     want = np.zeros(z.shape, dtype=bool)
