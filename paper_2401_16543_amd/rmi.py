@@ -27,9 +27,9 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
         report_every: int = 500, max_steps: int | None = None, precision: str = "fp64", keep_state: bool = False,
         dts=None, integrator: str = "ssp3", tol: float = 1e-3, flattener: float | None = None) -> dict:
     """One run; `dts` replays a recorded sequence of SSP-RK3 step sizes (the
-    summary's "dts" when keep_state is set) so that two runs can be compared state
-    for state.  integrator "ssp432" takes atol = rtol = tol and cfl as the
-    largest CFL number."""
+    summary's "dts" when keep_state is set: the step sizes taken, accepted ones
+    for ssp432) so that two runs can be compared state for state.  integrator
+    "ssp432" takes atol = rtol = tol and cfl as the largest CFL number."""
     import torch
 
     from . import inputs, kfvm
@@ -69,6 +69,7 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
         res = integrate(dev, U, t_end, atol=tol, rtol=tol, cfl_max=cfl,
                         max_steps=max_steps if max_steps is not None else 10 ** 7, on_step=on_step)
         t, steps = res["t"], res["accepted"] + res["rejected"]
+        taken = res["dts"]
     while integrator == "ssp3" and t < t_end - 1e-12 and (max_steps is None or steps < max_steps):
         if dts is not None:
             if steps >= len(dts):

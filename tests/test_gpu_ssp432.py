@@ -82,3 +82,31 @@ def test_error_controlled_vortex(K):
     assert abs(st["t"] - T) <= 1e-12
     assert st["accepted"] > 0 and st["rejected"] <= st["accepted"]
     assert e_ssp <= 1.05 * e_rk3
+
+
+@pytest.mark.parametrize("integrator", ["ssp3", "ssp432"])
+def test_richtmyer_meshkov_driver_short_run(K, oracle_mod, integrator):
+    """The Richtmyer-Meshkov driver on a coarse grid (1/32 spacing, 192 x 32
+    cells): a few steps of either integrator with the two-pass reconstruction
+    match the oracle taking the same step sizes."""
+    from paper_2401_16543_amd import rmi
+    say(f"case rmi driver {integrator}")
+    out = rmi.run(R=2, cells_per_unit=32, t_end=1.0, cfl=0.5 if integrator == "ssp3" else 1.0, indicator=True,
+                  max_steps=4, keep_state=True, integrator=integrator, tol=1e-3)
+    assert out["status"] == 0 and out["steps"] == 4
+    assert len(out["dts"]) == (4 if integrator == "ssp3" else out["accepted"]) > 0
+    U0, m = inputs.rmi(2, 32)
+    nx, ny = m["n"]
+    orc = oracle_mod.Oracle(2, 2, (nx, ny), dx=[m["dx"]] * 2, gamma=inputs.RMI_GAMMA, kxrcf_m=1.5)
+    orc.set_boundary(0, "inflow", "outflow", lower_state=m["inflow"])
+    orc.set_boundary(1, "reflecting", "reflecting")
+    U = U0.numpy().copy()
+    if integrator == "ssp3":
+        for dt in out["dts"]:
+            U = orc.step(U, dt)
+    else:                        # a rejected attempt leaves U as it was
+        for dt in out["dts"]:
+            U, _ = orc.step_ssp432(U, dt, 1e-3, 1e-3)
+    e = rel_err(out["U"].cpu().numpy(), U)
+    say(f"  {out['steps']} steps, t = {out['t']:.4f}, rel err vs oracle {e:.2e}")
+    assert e <= 1e-10
