@@ -46,6 +46,7 @@ class _Ctx(C.Structure):
         ("limiter", C.c_int), ("kappa", C.c_double), ("riemann", C.c_int),
         ("weno", C.c_int), ("flags", C.POINTER(C.c_uint8)), ("kxrcf_m", C.c_double),
         ("bc", C.c_int * 6), ("bc_state", C.c_double * 30), ("flat_k1", C.c_double),
+        ("cfl_max_axis", C.c_int),
     ]
 
 BC_KINDS = {"periodic": 0, "outflow": 1, "reflecting": 2, "inflow": 3}
@@ -264,6 +265,11 @@ class Oracle:
         self._call(self._lib.oracle_step_ssp432(C.byref(self._ctx), _ptr(U), float(dt), float(atol), float(rtol),
                                                 _ptr(out), C.byref(err)))
         return out, err.value
+
+    def set_cfl_form(self, form: str):
+        """The CFL step: "sum" (default) takes dt = cfl / max over cells of the sum
+        over axes of (|u_a| + c) / dx_a, "max_axis" of its largest term."""
+        self._ctx.cfl_max_axis = {"sum": 0, "max_axis": 1}[form]
 
     def cfl_dt(self, U, cfl):
         U = self._check_U(U)

@@ -78,6 +78,7 @@ typedef struct {
     int bc[3][2];          /* boundary condition per axis and side (lower, upper): BC_* below */
     double bc_state[3][2][MAXV];   /* conserved inflow state per axis and side */
     double flat_k1;        /* > 0: the flattener eta of the limiter bounds (flattener()); 0: eta = 0 */
+    int cfl_max_axis;      /* CFL step: 0 the sum over axes of (|u_a| + c) / dx_a, 1 its largest term */
 } oracle_ctx;
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTING = 2, BC_INFLOW = 3 };
@@ -850,7 +851,11 @@ int oracle_cfl_dt(const oracle_ctx *c, const double *U, double cfl, double *dt)
         load_cell(c, U, cell, u);
         if (!admissible(c, u)) { err = ERR_NONPHYSICAL; continue; }
         double cs = sqrt(c->gamma * pressure(c, u) / u[0]), s = 0.0;
-        for (int a = 0; a < c->dim; ++a) s += (fabs(u[1 + a] / u[0]) + cs) / c->dx[a];
+        for (int a = 0; a < c->dim; ++a) {
+            double r = (fabs(u[1 + a] / u[0]) + cs) / c->dx[a];
+            if (c->cfl_max_axis) s = r > s ? r : s;
+            else s += r;
+        }
         if (s > m) m = s;
     }
     *dt = cfl / m;

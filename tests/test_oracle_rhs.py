@@ -294,6 +294,29 @@ def test_cfl_dt(oracle_mod):
     assert math.isclose(dt, 0.4 / (((np.abs(u) + c) * n + (np.abs(v) + c) * n).max()), rel_tol=1e-14)
 
 
+def test_cfl_dt_max_axis(oracle_mod):
+    """The max-axis CFL form: dt from the largest single-axis ratio, never shorter
+    than the sum form's and at most d times longer; with one axis's spacing made
+    huge (its ratio vanishes) the two forms agree; for a flow along x on a square
+    grid the ratio is (|u| + c) n."""
+    d, n, gamma = 2, 8, 1.4
+    U = _smooth_U(d, n)
+    o = oracle_mod.Oracle(d, 2, (n, n))
+    dt_sum = o.cfl_dt(U, 0.4)
+    o.set_cfl_form("max_axis")
+    dt_max = o.cfl_dt(U, 0.4)
+    assert dt_sum < dt_max <= d * dt_sum
+    wide = oracle_mod.Oracle(d, 2, (n, n), dx=[1.0 / n, 1e12])
+    s_wide = wide.cfl_dt(U, 0.4)
+    wide.set_cfl_form("max_axis")
+    assert math.isclose(wide.cfl_dt(U, 0.4), s_wide, rel_tol=1e-12)
+    rho = np.full((n, n), 1.3)
+    ux, p = 0.7, 2.0
+    Ux = np.stack([rho, rho * ux, 0 * rho, p / (gamma - 1) + 0.5 * rho * ux * ux])
+    c = math.sqrt(gamma * p / 1.3)
+    assert math.isclose(o.cfl_dt(Ux, 0.4), 0.4 / ((abs(ux) + c) * n), rel_tol=1e-14)
+
+
 # ----------------------------------------------------------- paper's Table 1
 @pytest.mark.slow
 def test_isentropic_vortex_table1(oracle_mod):
