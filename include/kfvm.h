@@ -54,6 +54,7 @@ enum {
 
 enum { KFVM_FP64 = 0, KFVM_SPLIT_F16 = 1, KFVM_SPLIT_BF16 = 2 };   /* kfvm_set_precision */
 enum { KFVM_HLLC = 0, KFVM_HLL = 1 };                              /* kfvm_set_riemann */
+enum { KFVM_CFL_SUM = 0, KFVM_CFL_MAX_AXIS = 1 };                  /* kfvm_set_cfl_form */
 enum { KFVM_IND_NONE = 0, KFVM_IND_KXRCF = 1 };                    /* kfvm_set_indicator */
 enum { KFVM_BC_PERIODIC = 0, KFVM_BC_OUTFLOW = 1, KFVM_BC_REFLECTING = 2, KFVM_BC_INFLOW = 3 }; /* kfvm_set_boundary */
 
@@ -192,6 +193,12 @@ int kfvm_set_limiter(kfvm_ctx *ctx, int enabled, double kappa);
  * onset; k1 = 0 (the default) gives eta = 0.  Every precision mode supports it.
  * Errors: KFVM_ERR_ARG (k1 negative or not finite). */
 int kfvm_set_flattener(kfvm_ctx *ctx, double k1);
+
+/* The formula of kfvm_cfl_dt (section 6 caps steps by a CFL number without
+ * stating one): KFVM_CFL_SUM (default) takes dt = cfl / max over cells of
+ * sum_a (|u_a| + c) / dx_a, KFVM_CFL_MAX_AXIS the largest single term instead
+ * (steps up to dim times longer).  Errors: KFVM_ERR_ARG (unknown form). */
+int kfvm_set_cfl_form(kfvm_ctx *ctx, int form);
 
 /* KFVM_HLLC (default) or KFVM_HLL (section 6). */
 int kfvm_set_riemann(kfvm_ctx *ctx, int solver);

@@ -579,6 +579,14 @@ int kfvm_set_limiter(kfvm_ctx *c, int enabled, double kappa)
     return KFVM_OK;
 }
 
+int kfvm_set_cfl_form(kfvm_ctx *c, int form)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (form != KFVM_CFL_SUM && form != KFVM_CFL_MAX_AXIS) return fail(c, KFVM_ERR_ARG, "unknown CFL form");
+    c->geom.cfl_max_axis = form == KFVM_CFL_MAX_AXIS;
+    return KFVM_OK;
+}
+
 int kfvm_set_flattener(kfvm_ctx *c, double k1)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");

@@ -15,6 +15,7 @@ struct Geom {
     double dx[3];
     double gamma;
     int periodic;               // every axis periodic: ghost cells are a plain index wrap
+    int cfl_max_axis;           // CFL step: 0 the sum over axes of (|u_a| + c) / dx_a, 1 its largest term
     int bc[3][2];               // BC_* per axis and side (lower, upper)
     double bc_state[3][2][5];   // conserved inflow state per axis and side
 };

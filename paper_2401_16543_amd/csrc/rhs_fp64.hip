@@ -632,7 +632,10 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double *__restrict__ 
         const double cs = sqrt(g.gamma * pressure<D>(u, g.gamma) / u[0]);
         double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) s += (fabs(u[1 + a] / u[0]) + cs) / g.dx[a];
+        for (int a = 0; a < D; ++a) {
+            const double r = (fabs(u[1 + a] / u[0]) + cs) / g.dx[a];
+            s = g.cfl_max_axis ? fmax(s, r) : s + r;
+        }
         m = fmax(m, s);
     }
     // wave64 max, then across the block's waves

@@ -19,7 +19,7 @@ KFVM_HLLC, KFVM_HLL = 0, 1
 
 EXPORTED = [
     "kfvm_init", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream", "kfvm_set_precision",
-    "kfvm_set_limiter", "kfvm_set_flattener", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
+    "kfvm_set_limiter", "kfvm_set_flattener", "kfvm_set_cfl_form", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
     "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step", "kfvm_set_indicator", "kfvm_kxrcf",
@@ -73,6 +73,7 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_set_precision": ([vp, ip], ip),
         "kfvm_set_limiter": ([vp, ip, C.c_double], ip),
         "kfvm_set_flattener": ([vp, C.c_double], ip),
+        "kfvm_set_cfl_form": ([vp, ip], ip),
         "kfvm_set_riemann": ([vp, ip], ip),
         "kfvm_set_checking": ([vp, ip], ip),
         "kfvm_status": ([vp], ip),
@@ -238,6 +239,10 @@ class KFVM:
     def set_flattener(self, k1: float | None):
         """The limiter's flattener eta with onset k1 (None or 0: eta = 0)."""
         self._check(self.lib.kfvm_set_flattener(self._h, float(k1) if k1 else 0.0))
+
+    def set_cfl_form(self, form: str):
+        """The formula of cfl_dt: "sum" (default) or "max_axis"."""
+        self._check(self.lib.kfvm_set_cfl_form(self._h, {"sum": 0, "max_axis": 1}[form]))
 
     def set_riemann(self, solver: str):
         self._check(self.lib.kfvm_set_riemann(self._h, {"hllc": KFVM_HLLC, "hll": KFVM_HLL}[solver]))

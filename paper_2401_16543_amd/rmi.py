@@ -1,7 +1,7 @@
 """The Richtmyer-Meshkov run of section 6.3 on one GPU through the library.
 
     python -m paper_2401_16543_amd.rmi [--R 2] [--cells-per-unit 512] [--t-end 3.33]
-                                       [--integrator ssp3|ssp432] [--cfl 0.5]
+                                       [--integrator ssp3|ssp432] [--cfl 0.5] [--cfl-form sum]
                                        [--tol 1e-3] [--no-indicator] [--flattener K1]
                                        [--precision fp64] [--compare-fp64]
 
@@ -25,7 +25,8 @@ import time
 
 def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float = 0.5, indicator: bool = True,
         report_every: int = 500, max_steps: int | None = None, precision: str = "fp64", keep_state: bool = False,
-        dts=None, integrator: str = "ssp3", tol: float = 1e-3, flattener: float | None = None) -> dict:
+        dts=None, integrator: str = "ssp3", tol: float = 1e-3, flattener: float | None = None,
+        cfl_form: str = "sum") -> dict:
     """One run; `dts` replays a recorded sequence of SSP-RK3 step sizes (the
     summary's "dts" when keep_state is set: the step sizes taken, accepted ones
     for ssp432) so that two runs can be compared state for state.  integrator
@@ -44,6 +45,7 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
         dev.set_indicator("kxrcf", 1.5)
     if flattener:
         dev.set_flattener(flattener)
+    dev.set_cfl_form(cfl_form)
     dev.set_timing(True)
     dev.kernel_times()
     torch.cuda.synchronize()
@@ -91,7 +93,7 @@ def run(R: int = 2, cells_per_unit: int = 512, t_end: float = 3.33, cfl: float =
     flagged = float(dev.get_flags()[0].float().mean()) if indicator else 1.0
     nrhs = (4 if integrator == "ssp432" else 3) * steps
     out = {"problem": "Richtmyer-Meshkov, Ma 3, rho_D 2", "R": R, "grid": [nx, ny], "t": t, "steps": steps,
-            "precision": precision, "integrator": integrator, "flattener_k1": flattener,
+            "precision": precision, "integrator": integrator, "flattener_k1": flattener, "cfl_form": cfl_form,
             "rhs_evaluations": nrhs, "cfl": cfl, "indicator": "KXRCF m=3/2" if indicator else "none (WENO-AO everywhere)",
             "wall_s": wall, "wall_ms_per_rhs": wall / nrhs * 1e3,
             "device_ms_total": totals,
@@ -113,6 +115,8 @@ def main():
     ap.add_argument("--integrator", default="ssp3", choices=["ssp3", "ssp432"])
     ap.add_argument("--cfl", type=float, default=None, help="CFL number (ssp3, default 0.5) or its cap (ssp432, default 1)")
     ap.add_argument("--tol", type=float, default=1e-3, help="ssp432: atol = rtol")
+    ap.add_argument("--cfl-form", default="sum", choices=["sum", "max_axis"],
+                    help="CFL step from the sum over axes of (|u|+c)/dx (default) or its largest term")
     ap.add_argument("--flattener", type=float, default=None, help="the limiter flattener's onset k1 (default off)")
     ap.add_argument("--no-indicator", action="store_true")
     ap.add_argument("--max-steps", type=int, default=None)
@@ -125,10 +129,10 @@ def main():
         ap.error("--compare-fp64 replays SSP-RK3 step sizes: use --integrator ssp3")
     out = run(a.R, a.cells_per_unit, a.t_end, cfl, not a.no_indicator, max_steps=a.max_steps,
               precision=a.precision, keep_state=a.compare_fp64, integrator=a.integrator, tol=a.tol,
-              flattener=a.flattener)
+              flattener=a.flattener, cfl_form=a.cfl_form)
     if a.compare_fp64:
         ref = run(a.R, a.cells_per_unit, a.t_end, cfl, not a.no_indicator, precision="fp64", keep_state=True,
-                  dts=out["dts"], flattener=a.flattener)
+                  dts=out["dts"], flattener=a.flattener, cfl_form=a.cfl_form)
         out["l1_rho_vs_fp64"] = float((out["U"][0] - ref["U"][0]).abs().mean())
         out["fp64_wall_ms_per_rhs"] = ref["wall_ms_per_rhs"]
         out.pop("U")

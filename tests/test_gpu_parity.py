@@ -124,6 +124,25 @@ def test_ssp_rk3_trajectory_2d_64(K, oracle_mod):
     assert e <= TOL
 
 
+@pytest.mark.parametrize("d,n", [(2, (40, 24)), (3, (20, 12, 16))])
+@pytest.mark.parametrize("form", ["sum", "max_axis"])
+def test_cfl_dt_forms(K, oracle_mod, d, n, form):
+    """Both CFL formulas against the oracle on a field with unequal spacings."""
+    say(f"case cfl form {form} d={d}")
+    U = inputs.cell_averages(inputs.discontinuous(4, d, 4, 10.0, 100.0), max(n), 1.4, rule="midpoint", q=2)
+    U = U[(slice(None),) + tuple(slice(0, x) for x in reversed(n))].contiguous()
+    dx = [0.5 / n[a] * (1 + a) for a in range(d)]
+    orc = oracle_mod.Oracle(d, 2, n, dx=dx)
+    dev = K.KFVM(d, n, dx=dx, order=5)
+    orc.set_cfl_form(form)
+    dev.set_cfl_form(form)
+    dt_o, dt_g = orc.cfl_dt(U.numpy(), 0.7), dev.cfl_dt(U.cuda(), 0.7)
+    say(f"  dt {dt_g:.6e} (oracle {dt_o:.6e})")
+    assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+    with pytest.raises(K.KfvmError):
+        dev._check(dev.lib.kfvm_set_cfl_form(dev._h, 7))      # an unknown form
+
+
 @pytest.mark.parametrize("name,nsample", [("2d_jumps_1024", 600), ("3d_smooth_256", 160), ("3d_jumps_384_r3", 60)])
 def test_full_size_sampled(K, oracle_mod, name, nsample):
     """Full-size workloads: the GPU RHS over the whole grid (the benchmark's
