@@ -104,6 +104,8 @@ typedef struct {
                                     gate, the indicator or kfvm_set_flags chose) */
     long long cell_vars;         /* all (cell, variable) pairs */
     int error;                   /* sticky device error code (0 or KFVM_ERR_NONPHYSICAL) */
+    double min_rho, min_p;       /* least density and pressure over the admissible cells of the state passed
+                                    to the last kfvm_cfl_dt (NaN before the first call) */
 } kfvm_stats_t;
 
 /* Create a context for `mesh`.  order 5 selects R = 2, order 7 selects R = 3

@@ -25,6 +25,7 @@ struct kfvm_ctx {
     double *d_wch = nullptr;          // chunk-major copy of the tables (3D R = 3 FP64 path)
     kfvm::Work work{};
     double *d_dt = nullptr;
+    double min_rho = NAN, min_p = NAN;       // of the state of the last kfvm_cfl_dt
     std::vector<void *> allocs;
     std::string msg;
     // per-kernel timing (kfvm_set_timing): event pairs per launch, summed on query
@@ -298,10 +299,10 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     A((void **)&c->work.fbar, sizeof(double) * (size_t)dim * nv * ncell);
     A((void **)&c->work.stage[0], sizeof(double) * (size_t)nv * ncell);
     A((void **)&c->work.stage[1], sizeof(double) * (size_t)nv * ncell);
-    A((void **)&c->work.cfl_part, sizeof(double) * 1024);
+    A((void **)&c->work.cfl_part, sizeof(double) * 3 * 1024);
     A((void **)&c->work.err, sizeof(int) * 4);
     A((void **)&c->work.counts, sizeof(unsigned long long) * 2);
-    A((void **)&c->d_dt, sizeof(double));
+    A((void **)&c->d_dt, sizeof(double) * 3);
     if (rc != KFVM_OK) {
         g_init_msg = c->msg;
         kfvm_destroy(c);
@@ -544,8 +545,13 @@ int kfvm_cfl_dt(kfvm_ctx *c, const double *U, double cfl, double *dt_host)
     if (!(cfl > 0.0)) return fail(c, KFVM_ERR_ARG, "cfl must be positive");
     hipError_t e = kfvm::launch_cfl(c->dim, c->geom, c->work, U, cfl, c->d_dt, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "launch");
-    HIP_TRY(c, hipMemcpyAsync(dt_host, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    return sync_check(c);
+    double r[3];
+    HIP_TRY(c, hipMemcpyAsync(r, c->d_dt, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+    const int rc = sync_check(c);
+    *dt_host = r[0];
+    c->min_rho = r[1];
+    c->min_p = r[2];
+    return rc;
 }
 
 int kfvm_set_stream(kfvm_ctx *c, void *s)
@@ -625,6 +631,8 @@ int kfvm_stats(kfvm_ctx *c, kfvm_stats_t *out)
     HIP_TRY(c, hipMemcpy(&err, c->work.err, sizeof(int), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     out->cell_vars = (long long)c->geom.ncell * c->nvar;
+    out->min_rho = c->min_rho;
+    out->min_p = c->min_p;
     // counted from the limiter factors and the choices the last reconstruction left
     unsigned long long cnt[2] = {0, 0};
     if (!c->recon_done) {

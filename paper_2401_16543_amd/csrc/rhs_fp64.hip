@@ -621,15 +621,18 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double *__restrict__ 
                                                      int *__restrict__ err, Geom g)
 {
     constexpr int NV = D + 2;
-    __shared__ double red[256 / 64];
-    double m = 0.0;
+    __shared__ double red[3][256 / 64];
+    double m = 0.0, rmin = INFINITY, pmin = INFINITY;    // also the least density and pressure
     for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell;
          cell += (long)gridDim.x * blockDim.x) {
         double u[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + cell];
         if (!admissible<D>(u, g.gamma)) { *err = ERR_NONPHYSICAL; continue; }
-        const double cs = sqrt(g.gamma * pressure<D>(u, g.gamma) / u[0]);
+        const double p = pressure<D>(u, g.gamma);
+        rmin = fmin(rmin, u[0]);
+        pmin = fmin(pmin, p);
+        const double cs = sqrt(g.gamma * p / u[0]);
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -638,34 +641,67 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double *__restrict__ 
         }
         m = fmax(m, s);
     }
-    // wave64 max, then across the block's waves
+    // wave64 max (min), then across the block's waves
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    for (int off = 32; off > 0; off >>= 1) {
+        m = fmax(m, __shfl_xor(m, off, 64));
+        rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
+        pmin = fmin(pmin, __shfl_xor(pmin, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = m;
+        red[1][threadIdx.x >> 6] = rmin;
+        red[2][threadIdx.x >> 6] = pmin;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double r = red[0];
+        double r = red[0][0], a = red[1][0], b = red[2][0];
 #pragma unroll
-        for (int i = 1; i < 256 / 64; ++i) r = fmax(r, red[i]);
+        for (int i = 1; i < 256 / 64; ++i) {
+            r = fmax(r, red[0][i]);
+            a = fmin(a, red[1][i]);
+            b = fmin(b, red[2][i]);
+        }
         part[blockIdx.x] = r;
+        part[gridDim.x + blockIdx.x] = a;
+        part[2 * gridDim.x + blockIdx.x] = b;
     }
 }
 
+// dt[0] = cfl / (largest ratio), dt[1] the least density, dt[2] the least pressure
 __global__ __launch_bounds__(256) void k_cfl_final(const double *__restrict__ part, int nparts, double cfl,
                                                    double *__restrict__ dt)
 {
-    __shared__ double red[256 / 64];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, part[i]);
+    __shared__ double red[3][256 / 64];
+    double m = 0.0, a = INFINITY, b = INFINITY;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        m = fmax(m, part[i]);
+        a = fmin(a, part[nparts + i]);
+        b = fmin(b, part[2 * nparts + i]);
+    }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    for (int off = 32; off > 0; off >>= 1) {
+        m = fmax(m, __shfl_xor(m, off, 64));
+        a = fmin(a, __shfl_xor(a, off, 64));
+        b = fmin(b, __shfl_xor(b, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = m;
+        red[1][threadIdx.x >> 6] = a;
+        red[2][threadIdx.x >> 6] = b;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double r = red[0];
+        double r = red[0][0], ra = red[1][0], rb = red[2][0];
 #pragma unroll
-        for (int i = 1; i < 256 / 64; ++i) r = fmax(r, red[i]);
-        *dt = cfl / r;
+        for (int i = 1; i < 256 / 64; ++i) {
+            r = fmax(r, red[0][i]);
+            ra = fmin(ra, red[1][i]);
+            rb = fmin(rb, red[2][i]);
+        }
+        dt[0] = cfl / r;
+        dt[1] = ra;
+        dt[2] = rb;
     }
 }
 

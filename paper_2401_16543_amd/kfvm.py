@@ -49,7 +49,8 @@ class _Weights(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("limiter_cells", C.c_longlong), ("weno_cell_vars", C.c_longlong),
-                ("cell_vars", C.c_longlong), ("error", C.c_int)]
+                ("cell_vars", C.c_longlong), ("error", C.c_int), ("min_rho", C.c_double),
+                ("min_p", C.c_double)]
 
 
 _lib = None
@@ -361,4 +362,4 @@ class KFVM:
         s = _Stats()
         self._check(self.lib.kfvm_stats(self._h, C.byref(s)))
         return dict(limiter_cells=s.limiter_cells, weno_cell_vars=s.weno_cell_vars, cell_vars=s.cell_vars,
-                    error=s.error)
+                    error=s.error, min_rho=s.min_rho, min_p=s.min_p)

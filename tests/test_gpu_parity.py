@@ -136,9 +136,16 @@ def test_cfl_dt_forms(K, oracle_mod, d, n, form):
     dev = K.KFVM(d, n, dx=dx, order=5)
     orc.set_cfl_form(form)
     dev.set_cfl_form(form)
+    assert np.isnan(dev.stats()["min_rho"])                  # no CFL reduction yet
     dt_o, dt_g = orc.cfl_dt(U.numpy(), 0.7), dev.cfl_dt(U.cuda(), 0.7)
     say(f"  dt {dt_g:.6e} (oracle {dt_o:.6e})")
     assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+    # the same reduction reports the least density and pressure of the state
+    Un = U.numpy().reshape(d + 2, -1)
+    p = 0.4 * (Un[-1] - 0.5 * (Un[1:1 + d] ** 2).sum(0) / Un[0])
+    st = dev.stats()
+    assert st["min_rho"] == Un[0].min()
+    assert abs(st["min_p"] - p.min()) <= 1e-13 * p.min()
     with pytest.raises(K.KfvmError):
         dev._check(dev.lib.kfvm_set_cfl_form(dev._h, 7))      # an unknown form
 
