@@ -1,0 +1,59 @@
+"""The paper's Table 1 (section 6.1) on the GPU: L1 density error of the
+isentropic vortex after one period (t = 20, [-10, 10]^2 periodic) at 32^2 to
+256^2, with the linear S0 reconstruction (the table's label marks it as the
+scheme without WENO) and error-controlled time steps (SSP(4,3,2) here; the
+paper's 4-stage method at the same kind of tolerance), tight enough that the
+spatial error dominates.  The printed errors are the pins (tests/golden)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_16543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2401_16543_amd import kfvm
+    kfvm.load_library()
+    return kfvm
+
+
+def _vortex_error(K, R, n, tol):
+    from paper_2401_16543_amd.integrate import integrate
+    U0 = inputs.cell_averages(inputs.isentropic_vortex(GAMMA), n, GAMMA, rule="gauss", q=4).cuda()
+    dev = K.KFVM(2, (n, n), dx=[20.0 / n] * 2, order=2 * R + 1, gamma=GAMMA)
+    dev.set_checking(True)
+    dev.set_flags(torch.zeros((4, n * n), dtype=torch.uint8, device="cuda"))     # linear S0 everywhere
+    U = U0.clone()
+    res = integrate(dev, U, 20.0, atol=tol, rtol=tol, cfl_max=1.0)
+    assert abs(res["t"] - 20.0) < 1e-12
+    err = float((U[0] - U0[0]).abs().mean())
+    dev.close()
+    return err, res
+
+
+@pytest.mark.parametrize("R,ns,band", [(2, (32, 64, 128, 256), 0.03), (3, (32, 64, 128), 0.20)])
+def test_table1_isentropic_vortex(K, R, ns, band):
+    rows = np.loadtxt(__file__.rsplit("/", 1)[0] + "/golden/table1_isentropic_vortex.txt")
+    col = 1 if R == 2 else 2
+    errs = []
+    for n in ns:
+        ref = rows[list(rows[:, 0]).index(n), col]
+        err, res = _vortex_error(K, R, n, 1e-9)
+        errs.append(err)
+        say(f"case table1 R={R} n={n}: L1 {err:.3e}, paper {ref:.3e} (x{err / ref:.3f}), "
+            f"{res['accepted']} steps, {res['rejected']} rejected")
+        assert abs(err / ref - 1.0) <= band
+    eoc = [math.log(errs[i] / errs[i + 1], 2) for i in range(len(errs) - 1)]
+    say(f"  EOC {['%.2f' % e for e in eoc]}")
+    assert all(e > 2.5 for e in eoc)
