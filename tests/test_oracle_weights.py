@@ -219,3 +219,36 @@ def test_kernel_matrix_symmetric_on_unit_cells():
     with mpmath.workdps(30):
         for t in range(-4, 5):
             assert abs(W._kernel_avg_1d(mpmath.mpf(t), 5) - W._kernel_avg_1d(mpmath.mpf(-t), 5)) < 1e-28
+
+
+def _max_fourier_growth(R, a):
+    """Largest real part (times the spacing) of the semi-discrete linear-advection
+    symbol of the linear S0 scheme in 2D: upwind fluxes at the face Gauss points
+    of the cell's own reconstruction, a = advection velocity."""
+    T = W.tables(2, R)
+    pts = [tuple(float(v) for v in p) for p in W.face_points(2, R)]
+    s0 = np.asarray(T["s0"])
+    r = np.asarray(T["weights"][0])[:len(pts)]
+    nodes, gw = np.asarray(T["gl_nodes"]), np.asarray(T["gl_weights"])
+    th = np.linspace(-np.pi, np.pi, 181)
+    TX, TY = np.meshgrid(th, th, indexing="ij")
+    ph = np.exp(1j * (TX[..., None] * s0[None, None, :, 0] + TY[..., None] * s0[None, None, :, 1]))
+    sym = []
+    for axis in (0, 1):
+        face = [i for i, p in enumerate(pts) if abs(p[axis] - 0.5) < 1e-12]
+        sym.append(sum(gw[np.argmin(np.abs(nodes - pts[i][1 - axis]))] * (ph @ r[i]) for i in face))
+    lam = -(a[0] * (1 - np.exp(-1j * TX)) * sym[0] + a[1] * (1 - np.exp(-1j * TY)) * sym[1])
+    return lam.real.max()
+
+
+def test_linear_scheme_fourier_growth():
+    """A property of the tables, not a paper pin: the R = 2 linear scheme has no
+    growing Fourier mode for linear advection (up to 3e-4 / spacing for a flow
+    along an axis), while the R = 3 one has modes odd in the transverse index that
+    grow at up to 0.19 / spacing (flow along x), 0.011 / spacing diagonally.  They
+    are what the linear R = 3 scheme shows on the 256^2 vortex (design notes);
+    WENO-AO damps them."""
+    assert _max_fourier_growth(2, (1.0, 1.0)) <= 1e-12
+    assert _max_fourier_growth(2, (1.0, 0.0)) <= 5e-4
+    assert _max_fourier_growth(3, (1.0, 0.0)) > 0.15
+    assert 0.005 < _max_fourier_growth(3, (1.0, 1.0)) < 0.05
