@@ -811,7 +811,7 @@ __global__ __launch_bounds__((MixCfg<D, 2>::NT)) void k_gate_flags(const double 
     if (tb >= nblk) return;
     const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
     const double gam = g.gamma;
-    const Limiter off{0, 0.0};
+    const Limiter off{0, 0.0, 0.0};
     load_tile<D, 2, M::NT>(U, g, off, bx * C::TX - 2, by * C::TY - 2, D == 3 ? bz * C::TZ - 2 : 0, tile,
                            (double *)nullptr);
     for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];

@@ -1,6 +1,5 @@
 """Pins of the exact Riemann solver used as a reference by the Sod tests: the
 jump conditions across each wave and the relations inside a rarefaction."""
-import math
 
 import numpy as np
 import pytest

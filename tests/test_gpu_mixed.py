@@ -3,7 +3,6 @@
 Its bar is accuracy, not bit parity: the contractions run on FP16/BF16 hi/lo
 operands with FP32 accumulation.  Right-hand sides are compared relative to the
 largest magnitude per variable; trajectories by the L1 density difference."""
-import sys
 
 import numpy as np
 import pytest
