@@ -61,15 +61,17 @@ def test_table1_isentropic_vortex(K, R, ns, band):
 
 def test_vortex_driver(K):
     """The command-line driver of the study: the linear scheme reproduces the
-    table's R = 2 errors at 32^2 and 64^2; WENO-AO everywhere and the two-pass
-    reconstruction run the same problem to a finite, converging error."""
+    table's R = 2 errors at 32^2 and 64^2 on the FP64 path and on both split
+    matrix-core paths; WENO-AO everywhere and the two-pass reconstruction run
+    the same problem to a finite, converging error."""
     from paper_2401_16543_amd import vortex
     rows = np.loadtxt(__file__.rsplit("/", 1)[0] + "/golden/table1_isentropic_vortex.txt")
-    out = vortex.run(R=2, ns=(32, 64), scheme="linear", tol=1e-9)
-    for r in out["results"]:
-        ref = rows[list(rows[:, 0]).index(r["n"]), 1]
-        say(f"case vortex driver linear n={r['n']}: L1 {r['l1_rho']:.3e}, paper {ref:.3e}")
-        assert abs(r["l1_rho"] / ref - 1.0) <= 0.03
+    for precision in ("fp64", "split_f16", "split_bf16"):
+        out = vortex.run(R=2, ns=(32, 64), scheme="linear", tol=1e-9, precision=precision)
+        for r in out["results"]:
+            ref = rows[list(rows[:, 0]).index(r["n"]), 1]
+            say(f"case vortex driver linear {precision} n={r['n']}: L1 {r['l1_rho']:.3e}, paper {ref:.3e}")
+            assert abs(r["l1_rho"] / ref - 1.0) <= 0.03
     for scheme in ("weno", "kxrcf"):
         out = vortex.run(R=2, ns=(32, 64), scheme=scheme, tol=1e-6)
         e = [r["l1_rho"] for r in out["results"]]
