@@ -116,6 +116,15 @@ typedef struct {
  * current HIP device.  Defaults: FP64, HLLC, limiter on with kappa = 0.5. */
 int kfvm_init(kfvm_ctx **ctx, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights);
 
+/* kfvm_init with tables built at kernel length scale ell_hat = l / Delta (in
+ * cells) instead of 5, the paper's fixed choice (section 5.1; l is the
+ * hyperparameter of the squared-exponential kernel of section 2.1).  The
+ * polynomial part keeps the design order at any l; the 3D R = 3 weights grow
+ * with l (largest face-point weight ~2 at 5, ~35 at 20, ~1600 at 100), which
+ * amplifies rounding.  ell_hat outside (0, 100] (or NaN) returns KFVM_ERR_ARG
+ * before any device call; otherwise as kfvm_init with weights == NULL. */
+int kfvm_init_length_scale(kfvm_ctx **ctx, const kfvm_mesh *mesh, int order, double gamma, double ell_hat);
+
 /* dUdt = L(U): the right-hand side on the whole grid.  U and dUdt are distinct
  * device buffers of nvar * ncells float64 (aliasing is rejected). */
 int kfvm_rhs(kfvm_ctx *ctx, const double *U, double *dUdt);

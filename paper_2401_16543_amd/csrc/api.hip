@@ -247,7 +247,8 @@ int prepare_mixed(kfvm_ctx *c, int mode)
 
 extern "C" {
 
-int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights)
+static int init_context(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights,
+                        double ell_hat)
 {
     if (!out || !mesh) return fail(nullptr, KFVM_ERR_ARG, "null argument");
     *out = nullptr;
@@ -285,7 +286,7 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
         }
         std::memcpy(host.data(), weights->tables, sizeof(double) * ntab);
     } else {
-        if (kfvm_weights_build(dim, R, 5.0, host.data(), ntab) != ntab) {
+        if (kfvm_weights_build(dim, R, ell_hat, host.data(), ntab) != ntab) {
             delete c;
             return fail(nullptr, KFVM_ERR_STATE, "weight build failed");
         }
@@ -341,6 +342,19 @@ int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, co
     }
     *out = c;
     return KFVM_OK;
+}
+
+int kfvm_init(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, const kfvm_weights *weights)
+{
+    return init_context(out, mesh, order, gamma, weights, 5.0);
+}
+
+int kfvm_init_length_scale(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double gamma, double ell_hat)
+{
+    if (out) *out = nullptr;
+    if (!(ell_hat > 0.0 && ell_hat <= 100.0))
+        return fail(nullptr, KFVM_ERR_ARG, "ell_hat must lie in (0, 100]");
+    return init_context(out, mesh, order, gamma, nullptr, ell_hat);
 }
 
 static void record_event(void *self, int kind, hipStream_t s, int begin)

@@ -18,7 +18,8 @@ KFVM_FP64, KFVM_SPLIT_F16, KFVM_SPLIT_BF16 = 0, 1, 2
 KFVM_HLLC, KFVM_HLL = 0, 1
 
 EXPORTED = [
-    "kfvm_init", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream", "kfvm_set_precision",
+    "kfvm_init", "kfvm_init_length_scale", "kfvm_rhs", "kfvm_step", "kfvm_cfl_dt", "kfvm_set_stream",
+    "kfvm_set_precision",
     "kfvm_set_limiter", "kfvm_set_flattener", "kfvm_set_cfl_form", "kfvm_set_riemann", "kfvm_set_checking", "kfvm_status", "kfvm_stats",
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
@@ -67,6 +68,7 @@ def load_library(path: str = _LIB_PATH):
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
     sig = {
         "kfvm_init": ([C.POINTER(vp), C.POINTER(_Mesh), ip, C.c_double, C.POINTER(_Weights)], ip),
+        "kfvm_init_length_scale": ([C.POINTER(vp), C.POINTER(_Mesh), ip, C.c_double, C.c_double], ip),
         "kfvm_rhs": ([vp, vp, vp], ip),
         "kfvm_step": ([vp, vp, C.c_double], ip),
         "kfvm_cfl_dt": ([vp, vp, C.c_double, dp], ip),
@@ -122,7 +124,10 @@ class KFVM:
     """One context of the library for a periodic box; U tensors are float64 on the GPU,
     shaped (nvar, ny, nx) in 2D or (nvar, nz, ny, nx) in 3D."""
 
-    def __init__(self, dim: int, n, dx=None, order: int = 5, gamma: float = 1.4, weights=None):
+    def __init__(self, dim: int, n, dx=None, order: int = 5, gamma: float = 1.4, weights=None,
+                 ell_hat: float | None = None):
+        """weights: tables to use instead of the library's own; ell_hat: the kernel
+        length scale in cells for the library's own tables (default 5)."""
         if not torch.cuda.is_available():
             raise RuntimeError("KFVM needs a ROCm GPU; none is visible")
         self.lib = load_library()
@@ -143,7 +148,12 @@ class KFVM:
         if weights is not None:
             wp, self._keep = self._pack_weights(weights)
         h = C.c_void_p()
-        rc = self.lib.kfvm_init(C.byref(h), C.byref(mesh), order, gamma, wp)
+        if ell_hat is not None:
+            if weights is not None:
+                raise ValueError("pass either weights or ell_hat")
+            rc = self.lib.kfvm_init_length_scale(C.byref(h), C.byref(mesh), order, gamma, float(ell_hat))
+        else:
+            rc = self.lib.kfvm_init(C.byref(h), C.byref(mesh), order, gamma, wp)
         if rc != KFVM_OK:
             raise KfvmError(rc, self.lib.kfvm_last_error(None).decode())
         self._h = h

@@ -2,7 +2,7 @@
 
     python -m paper_2401_16543_amd.vortex [--R 2] [--n 32 64 128 256]
                                           [--scheme linear|weno|kxrcf|gate] [--tol 1e-9]
-                                          [--precision fp64|split_f16|split_bf16]
+                                          [--precision fp64|split_f16|split_bf16] [--ell 5]
 
 The vortex on the periodic [-10, 10]^2 returns to its initial position at
 t = 20; the L1 density error is the mean |rho(20) - rho(0)| over the cell
@@ -23,7 +23,7 @@ import time
 
 
 def run(R: int = 2, ns=(32, 64, 128, 256), scheme: str = "linear", tol: float = 1e-9,
-        precision: str = "fp64") -> dict:
+        precision: str = "fp64", ell_hat: float = 5.0) -> dict:
     import torch
 
     from . import inputs, kfvm
@@ -33,7 +33,7 @@ def run(R: int = 2, ns=(32, 64, 128, 256), scheme: str = "linear", tol: float = 
     rows = []
     for n in ns:
         U0 = inputs.cell_averages(spec, n, gamma, rule="gauss", q=4).cuda()
-        dev = kfvm.KFVM(2, (n, n), dx=[20.0 / n] * 2, order=2 * R + 1, gamma=gamma)
+        dev = kfvm.KFVM(2, (n, n), dx=[20.0 / n] * 2, order=2 * R + 1, gamma=gamma, ell_hat=ell_hat)
         dev.set_precision(precision)
         if scheme == "linear":
             dev.set_flags(torch.zeros((4, n * n), dtype=torch.uint8, device="cuda"))
@@ -60,7 +60,7 @@ def run(R: int = 2, ns=(32, 64, 128, 256), scheme: str = "linear", tol: float = 
     for a, b in zip(rows, rows[1:]):
         b["eoc"] = math.log(a["l1_rho"] / b["l1_rho"], 2)
     return {"problem": "isentropic vortex, t = 20", "R": R, "scheme": scheme, "tol": tol,
-            "precision": precision, "results": rows}
+            "precision": precision, "ell_hat": ell_hat, "results": rows}
 
 
 def main():
@@ -71,9 +71,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--precision", default=None, choices=["fp64", "split_f16", "split_bf16"],
                     help="default fp64, split_f16 for the gate")
+    ap.add_argument("--ell", type=float, default=5.0, help="kernel length scale in cells (the paper's 5)")
     a = ap.parse_args()
     precision = a.precision or ("split_f16" if a.scheme == "gate" else "fp64")
-    print(json.dumps(run(a.R, a.n, a.scheme, a.tol, precision)), flush=True)
+    print(json.dumps(run(a.R, a.n, a.scheme, a.tol, precision, a.ell)), flush=True)
 
 
 if __name__ == "__main__":

@@ -189,6 +189,27 @@ def test_weights_passed_in_match_built(K):
     assert rel_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-14
 
 
+def test_length_scale_entry_point(K, oracle_mod):
+    """Tables at another kernel length scale (l = 20 cells): the library's own
+    binary128 build through kfvm_init_length_scale against the oracle with its
+    50-digit tables at the same l, RHS to 1e-12; l = 5 through the entry point
+    is the default init, bit for bit."""
+    from oracle import weights as W
+    say("case length scale")
+    d, R, n = 2, 2, 32
+    U = _state("jumps", d, n, 3)
+    a = K.KFVM(d, (n, n), order=5, ell_hat=5.0).rhs(U.cuda())
+    b = K.KFVM(d, (n, n), order=5).rhs(U.cuda())
+    assert torch.equal(a, b)
+    T = dict(W.tables(d, R))
+    T["weights"] = [W.stencil_weights(d, R, q, ell_hat=20) for q in range(len(T["weights"]))]
+    ref = oracle_mod.Oracle(d, R, (n, n), tables=T).rhs(U.numpy())
+    got = K.KFVM(d, (n, n), order=5, ell_hat=20.0).rhs(U.cuda()).cpu().numpy()
+    e, moved = rel_err(got, ref), rel_err(got, b.cpu().numpy())
+    say(f"  rel err vs oracle at l = 20: {e:.3e}; change from l = 5: {moved:.3e}")
+    assert e <= TOL and moved > 1e-8
+
+
 def test_deterministic(K):
     say("case determinism")
     d, n = 3, 16
