@@ -14,7 +14,7 @@ def _smooth_U(d, n, seed=11, M=4, gamma=1.4, q=4):
 
 
 # ------------------------------------------------------------------ invariants
-@pytest.mark.parametrize("d,R,n", [(2, 2, 12), (2, 3, 12), (3, 2, 8)])
+@pytest.mark.parametrize("d,R,n", [(2, 2, 12), (2, 3, 12), (3, 2, 8), (3, 3, 8)])
 def test_constant_state_is_steady(oracle_mod, d, R, n):
     o = oracle_mod.Oracle(d, R, (n,) * d)
     U = np.empty((d + 2,) + (n,) * d)
@@ -26,7 +26,7 @@ def test_constant_state_is_steady(oracle_mod, d, R, n):
     assert np.abs(L).max() < 1e-11
 
 
-@pytest.mark.parametrize("d,R,n", [(2, 2, 16), (2, 3, 16), (3, 2, 8)])
+@pytest.mark.parametrize("d,R,n", [(2, 2, 16), (2, 3, 16), (3, 2, 8), (3, 3, 8)])
 def test_periodic_conservation(oracle_mod, d, R, n):
     U = inputs.cell_averages(inputs.discontinuous(5, d, 3, 10.0, 50.0), n, 1.4, rule="midpoint", q=4).numpy()
     o = oracle_mod.Oracle(d, R, (n,) * d)
@@ -36,7 +36,7 @@ def test_periodic_conservation(oracle_mod, d, R, n):
     assert np.all(np.abs(tot) <= 1e-13 * scale)
 
 
-@pytest.mark.parametrize("d,R,n", [(2, 2, 16), (2, 3, 16), (3, 2, 8)])
+@pytest.mark.parametrize("d,R,n", [(2, 2, 16), (2, 3, 16), (3, 2, 8), (3, 3, 8)])
 def test_mirror_and_rotation_symmetry(oracle_mod, d, R, n):
     U = inputs.cell_averages(inputs.discontinuous(6, d, 3, 10.0, 50.0), n, 1.4, rule="midpoint", q=4).numpy()
     o = oracle_mod.Oracle(d, R, (n,) * d)
@@ -56,6 +56,74 @@ def test_mirror_and_rotation_symmetry(oracle_mod, d, R, n):
     Ls = np.swapaxes(Ls, -1, -2).copy()
     Ls[[1, 2]] = Ls[[2, 1]]
     assert np.abs(Ls - L).max() <= tol
+
+
+def _one_sided_ramp(d, n, lam):
+    """Cells at or below the centre's x index hold one admissible state; cells
+    past it add lam * (x - x_c) * g.  The centre's -x cone (cells with
+    -x >= |y|, |z|) then sees constant data, every other stencil the ramp."""
+    nv = d + 2
+    base = np.array([1.0, 0.3, -0.2] + ([0.1] if d == 3 else []) + [2.5])
+    g = np.array([0.3, 0.2, -0.1] + ([0.15] if d == 3 else []) + [0.5])
+    U = np.empty((nv,) + (n,) * d)
+    x = np.arange(n) - n // 2
+    ramp = np.maximum(x, 0).astype(float)       # along the last array axis (x)
+    for k in range(nv):
+        U[k] = base[k] + lam * g[k] * ramp
+    cell = sum((n // 2) * n ** a for a in range(d))
+    return U, cell
+
+
+@pytest.mark.parametrize("d,R", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_nonlinear_weights_flat_substencil_limit(oracle_mod, d, R):
+    """eq. nlinWts pinned by its limit for an exactly flat substencil (section
+    3.3): the -x cone of the centre sees constant data, so its smoothness
+    indicator is zero to rounding and only epsilon = 1e-40 bounds its weight.
+    Then the normalised weights go to that cone, and omega_0 / gamma_0 tends to
+    eps / (gamma_cone beta_0^2): scaling the data by lambda scales beta_0 by
+    lambda^2 and the ratio by lambda^-4 (the indicator enters squared), and the
+    ratio times gamma_cone beta_0^2 is epsilon itself.  A wrong epsilon, beta
+    for beta^2, a wrong linear weight or a missing normalisation each break one
+    of the two."""
+    from oracle import weights as W
+    n = 2 * R + 4
+    o = oracle_mod.Oracle(d, R, (n,) * d)
+    cone = 3                                   # stencil order: S0, S1, +x, -x, ...
+    gam = W.linear_weights(d)
+    lams = (1e-2, 1e-3)
+    r, b0 = [], []
+    for lam in lams:
+        U, cell = _one_sided_ramp(d, n, lam)
+        r.append(o.omega_ratio(U)[:, cell].astype(np.float64))
+        beta = o.smoothness(U, cell)
+        assert np.all(beta[:, cone] ** 2 < 1e-50)          # flat: zero to rounding
+        assert np.all(np.delete(beta, cone, axis=1) ** 2 > 1e-30)
+        b0.append(beta[:, 0])
+    # lambda^-4 scaling of the ratio (float32 output: 1e-6 relative)
+    assert np.allclose(r[1] / r[0], (lams[0] / lams[1]) ** 4, rtol=1e-5, atol=0), r[1] / r[0]
+    for rr, bb in zip(r, b0):
+        assert np.allclose(rr * gam[cone] * bb ** 2, 1e-40, rtol=1e-5, atol=0), rr * gam[cone] * bb ** 2
+
+
+@pytest.mark.parametrize("d,R", [(2, 2), (3, 2)])
+def test_nonlinear_weights_equal_indicators(oracle_mod, d, R):
+    """eq. nlinWts with every stencil seeing the same linear data: all smoothness
+    indicators are equal (|grad|^2, the closed form of the indicator pin), so
+    the normalised nonlinear weights are the linear weights and
+    omega_0 / gamma_0 = 1 (to the float32 output's rounding)."""
+    n = 2 * R + 4
+    o = oracle_mod.Oracle(d, R, (n,) * d)
+    nv = d + 2
+    U = np.empty((nv,) + (n,) * d)
+    x = (np.arange(n) - n // 2).astype(float)
+    base = np.array([1.0, 0.3, -0.2] + ([0.1] if d == 3 else []) + [2.5])
+    g = np.array([0.3, 0.2, -0.1] + ([0.15] if d == 3 else []) + [0.5])
+    for k in range(nv):
+        U[k] = base[k] + 1e-3 * g[k] * x
+    cell = sum((n // 2) * n ** a for a in range(d))
+    beta = o.smoothness(U, cell)
+    assert np.allclose(beta, beta[:, :1], rtol=1e-9)
+    assert np.abs(o.omega_ratio(U)[:, cell] - 1.0).max() <= 2e-7
 
 
 def test_rhs_cells_matches_whole_grid(oracle_mod):

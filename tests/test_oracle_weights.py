@@ -51,6 +51,14 @@ def test_degrees_and_derivative_counts():
         assert len(W.derivative_indices(d, R)) == GOLDEN[f"n_derivs_{d}d_R{R}"]
 
 
+def test_paper_constants_used_by_oracle():
+    """The oracle's epsilon of the nonlinear weights (section 3.3) and its kernel
+    length scale in cells (l = 5 Delta, sections 5.1 and 6) are the printed ones."""
+    from oracle import core
+    assert core.EPS_WENO == GOLDEN["eps_weno"]
+    assert W.ELL_HAT == GOLDEN["ell_over_dx"]
+
+
 def test_linear_weights():
     g2, g3 = W.linear_weights(2), W.linear_weights(3)
     assert g2[0] == GOLDEN["gamma_hi"]
@@ -83,7 +91,7 @@ def _gl_avg(f, cell, d, q=10):
     return tot
 
 
-@pytest.mark.parametrize("d,R", [(2, 2), (2, 3), (3, 2)])
+@pytest.mark.parametrize("d,R", [(2, 2), (2, 3), (3, 2), (3, 3)])
 def test_polynomial_exactness(d, R):
     """r . (cell averages of a polynomial of degree <= p_q) equals its value at x*
     and the derivatives at 0 (the constraint P^T r = S, section 2.1)."""
@@ -154,11 +162,13 @@ def test_kernel_part_reproduced_2d():
 
 
 def test_brute_force_high_precision_2d_r2():
-    # an 80-digit solve of every 2D R = 2 stencil agrees with the 50-digit
-    # tables to within rounding of the float64 result
+    # an 80-digit solve of every 2D R = 2 stencil at the paper's length scale
+    # (l = 5 Delta, from the golden file) agrees with the 50-digit tables the
+    # oracle uses to within rounding of the float64 result
     T = W.tables(2, 2)
+    ell = GOLDEN["ell_over_dx"]
     for q in range(len(T["members"])):
-        hi = W.stencil_weights.__wrapped__(2, 2, q, W.ELL_HAT, 80)
+        hi = W.stencil_weights.__wrapped__(2, 2, q, ell, 80)
         lo = T["weights"][q]
         scale = np.abs(hi).max(axis=1, keepdims=True)
         assert np.all(np.abs(hi - lo) <= 2 * np.finfo(float).eps * scale)
@@ -175,7 +185,7 @@ def test_row_sums(d, R):
         assert np.all(np.abs(tab[npt:].sum(1)) <= 1e-15 * s[npt:] * tab.shape[1])
 
 
-@pytest.mark.parametrize("d,R", [(2, 2), (3, 2), (2, 3)])
+@pytest.mark.parametrize("d,R", [(2, 2), (3, 2), (2, 3), (3, 3)])
 def test_mirror_and_rotation_symmetry(d, R):
     """Mirroring x -> -x maps S0 to itself, the +x cone to the -x cone and the
     upper x-face points to the lower ones (section 3.1); permuting x and y does
