@@ -131,9 +131,11 @@ int kfvm_rhs(kfvm_ctx *ctx, const double *U, double *dUdt);
 
 /* One SSP-RK3 step of size dt on U, in place:
  *   U1 = U + dt L(U),  U2 = 3/4 U + 1/4 (U1 + dt L(U1)),  U <- 1/3 U + 2/3 (U2 + dt L(U2)).
- * If a non-physical state is met, the contents of U are unspecified and the
- * error is reported by kfvm_status / kfvm_stats (or returned, see
- * kfvm_set_checking). */
+ * If any stage meets a non-physical state (a cell average or reconstructed
+ * state with rho <= 0, p <= 0 or a non-finite value, or a non-finite flux), U is
+ * left unmodified and KFVM_ERR_NONPHYSICAL is reported by kfvm_status /
+ * kfvm_stats (or returned, see kfvm_set_checking).  The decision is taken on
+ * the device, in stream order: the call does not synchronise for it. */
 int kfvm_step(kfvm_ctx *ctx, double *U, double dt);
 
 /* One step of SSP(4,3,2) (section 6): the four-stage third-order SSP Runge-Kutta

@@ -485,12 +485,17 @@ static int prepare_flags(kfvm_ctx *c, const double *U, kfvm::Work &w)
     return rc;
 }
 
-static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt)
+// err (optional): the error word this stage's kernels raise instead of the
+// sticky one; guard (optional): the update writes nothing while *guard != 0
+static int stage_call(kfvm_ctx *c, const double *U0, const double *Uin, double *out, int stage, double dt,
+                      int *err = nullptr, const int *guard = nullptr)
 {
     hipError_t e;
     kfvm::Work w;
     int rc = prepare_flags(c, Uin, w);
     if (rc != KFVM_OK) return rc;
+    if (err) w.err = err;
+    w.guard = guard;
     if (c->precision == KFVM_FP64) {
         rc = ensure_face64(c);
         if (rc != KFVM_OK) return rc;
@@ -523,9 +528,17 @@ int kfvm_step(kfvm_ctx *c, double *U, double dt)
     if (!U) return fail(c, KFVM_ERR_ARG, "null buffer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, KFVM_ERR_ARG, "dt must be positive and finite");
     double *U1 = c->work.stage[0], *U2 = c->work.stage[1];
-    int rc = stage_call(c, U, U, U1, 1, dt);
-    if (rc == KFVM_OK) rc = stage_call(c, U, U1, U2, 2, dt);
-    if (rc == KFVM_OK) rc = stage_call(c, U, U2, U, 3, dt);
+    // the step's own error word: cleared first, raised by any stage, read by the
+    // last stage's update (which then leaves U as it was), then merged into the
+    // sticky word; all stream-ordered, no host synchronisation
+    int *step_err = c->work.err + 1;
+    hipError_t e = kfvm::launch_err_reset(step_err, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    int rc = stage_call(c, U, U, U1, 1, dt, step_err);
+    if (rc == KFVM_OK) rc = stage_call(c, U, U1, U2, 2, dt, step_err);
+    if (rc == KFVM_OK) rc = stage_call(c, U, U2, U, 3, dt, step_err, step_err);
+    e = kfvm::launch_err_merge(c->work.err, step_err, c->stream);
+    if (rc == KFVM_OK && e != hipSuccess) return hip_fail(c, e, "launch");
     if (rc == KFVM_OK && c->checking) rc = sync_check(c);
     return rc;
 }

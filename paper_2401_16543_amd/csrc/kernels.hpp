@@ -33,7 +33,8 @@ struct Work {
     double *fbar;      // [dim][nvar][ncell] Gauss-integrated flux through each cell's lower faces
     double *stage[2];  // [nvar][ncell] Runge-Kutta stage states
     double *cfl_part;  // per-block maxima of the CFL reduction
-    int *err;          // sticky device error code
+    int *err;          // device error code the kernels raise (sticky word, or a step's own word)
+    const int *guard;  // optional: the update writes nothing while *guard != 0 (a step's last stage)
     unsigned long long *counts;  // [2] scratch of kfvm_stats: limiter cells, WENO (cell, var) pairs
     const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
     float *inc32;      // [n_pts][nvar][ncell] blended increments w_s - W_c (split-precision path)
@@ -79,6 +80,10 @@ hipError_t launch_rhs_fp64(int dim, int R, const Geom &g, const Tables &t, const
                            hipStream_t s, const Timing &tm);
 hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0, const double *Uin, double *out,
                          int stage, double dt, hipStream_t s);
+// *word = 0, and (merge) *sticky = *word where it is set: one thread each, so a
+// caller's stream order keeps them and no memset node enters a captured graph
+hipError_t launch_err_reset(int *word, hipStream_t s);
+hipError_t launch_err_merge(int *sticky, const int *word, hipStream_t s);
 // Learned troubled-cell gate fused into the split-precision reconstruction
 // (w == nullptr: no gate).  w: BF16 operand slots of W1 and W2 (8 values per lane
 // and slot, see rhs_mixed.hip); vec: b1[32], b2[32], w3[32], b3.

@@ -544,15 +544,19 @@ __global__ __launch_bounds__(256) void k_flux(const double *__restrict__ U, cons
 }
 
 // ----------------------------------------------------------------- update ---
+// U0 and out may be the same array (the last stage of a step in place): each
+// thread reads U0[i] before it writes out[i], so they carry no __restrict__.
+// guard (optional): nothing is written while *guard != 0, which leaves `out`
+// as it was when an earlier kernel of the step met a non-physical state.
 template <int D>
 __global__ __launch_bounds__(256) void k_update(const double *__restrict__ fbar, const double *__restrict__ fbar_top,
-                                                long plane, const double *__restrict__ U0,
-                                                const double *__restrict__ Uin, double *__restrict__ out, Geom g,
-                                                int stage, double dt)
+                                                long plane, const double *U0, const double *__restrict__ Uin,
+                                                double *out, Geom g, int stage, double dt, const int *guard)
 {
     constexpr int NV = D + 2;
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
+    if (guard && *guard != 0) return;
     const int cx = (int)(cell % g.n[0]), cy = (int)((cell / g.n[0]) % g.n[1]);
     const int cz = (int)(cell / ((long)g.n[0] * g.n[1]));
     const int c[3] = {cx, cy, cz};
@@ -788,7 +792,7 @@ hipError_t rhs_impl(const Geom &g, const Tables &t, const Work &w, const Limiter
     mark(KT_FLUX, 0);
     mark(KT_UPDATE, 1);
     hipLaunchKernelGGL((k_update<D>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g, stage,
-                       dt);
+                       dt, w.guard);
     mark(KT_UPDATE, 0);
     return hipGetLastError();
 }
@@ -867,10 +871,30 @@ hipError_t launch_update(int dim, const Geom &g, const Work &w, const double *U0
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
     if (dim == 2)
         hipLaunchKernelGGL((k_update<2>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g,
-                           stage, dt);
+                           stage, dt, w.guard);
     else
         hipLaunchKernelGGL((k_update<3>), dim3(nb), dim3(256), 0, s, w.fbar, w.fbar_top, w.plane, U0, Uin, out, g,
-                           stage, dt);
+                           stage, dt, w.guard);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_err_reset(int *word) { *word = 0; }
+__global__ void k_err_merge(int *sticky, const int *word)
+{
+    if (*word != 0) *sticky = *word;
+}
+}  // namespace
+
+hipError_t launch_err_reset(int *word, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_err_reset, dim3(1), dim3(1), 0, s, word);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_merge(int *sticky, const int *word, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_err_merge, dim3(1), dim3(1), 0, s, sticky, word);
     return hipGetLastError();
 }
 

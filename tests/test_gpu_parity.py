@@ -233,6 +233,37 @@ def test_nonphysical_input_is_reported(K):
     assert dev.status() == K.KFVM_OK        # cleared
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split_f16"])
+def test_step_leaves_state_on_nonphysical(K, precision):
+    """The non-physical contract of kfvm_step: when a stage meets a non-physical
+    state, U is left unmodified (bitwise) and the error is reported, with the
+    check on (returned by the step) and off (kfvm_status afterwards); a later
+    step from an admissible state runs normally."""
+    say(f"case step nonphysical {precision}")
+    d, n = 2, 16
+    U = _state("smooth", d, n, 6)
+    U[3, 4, 5] = 0.0                 # negative pressure in one cell
+    dev = K.KFVM(d, (n, n), order=5)
+    dev.set_precision(precision)
+    Ud = U.cuda()
+    before = Ud.clone()
+    dev.set_checking(True)
+    with pytest.raises(K.KfvmError) as ei:
+        dev.step(Ud, 1e-3)
+    assert ei.value.code == K.KFVM_ERR_NONPHYSICAL
+    assert torch.equal(Ud, before)
+    dev.set_checking(False)
+    dev.step(Ud, 1e-3)
+    assert dev.status() == K.KFVM_ERR_NONPHYSICAL
+    assert torch.equal(Ud, before)
+    assert dev.status() == K.KFVM_OK        # cleared
+    good = _state("smooth", d, n, 6).cuda()
+    g0 = good.clone()
+    dev.step(good, 1e-3)
+    assert dev.status() == K.KFVM_OK
+    assert not torch.equal(good, g0) and bool(torch.isfinite(good).all())
+
+
 def test_bad_arguments_are_rejected(K):
     say("case bad args")
     with pytest.raises(K.KfvmError):
