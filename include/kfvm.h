@@ -157,6 +157,25 @@ int kfvm_step_ssp432(kfvm_ctx *ctx, const double *U, double *U_out, double dt, d
  * written to host memory. */
 int kfvm_cfl_dt(kfvm_ctx *ctx, const double *U, double cfl, double *dt_host);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): kfvm_cfl_dt with its result
+ * left in device memory and no allocation of any kind in the call.
+ * out_dev: caller-owned device buffer of 3 float64 on the context's device;
+ * out_dev[0] = cfl / max_c sum_d (|u_d| + c_s) / Delta_d (or the largest-axis
+ * form, kfvm_set_cfl_form), out_dev[1] and out_dev[2] the least density and
+ * pressure over the admissible cells: the values kfvm_cfl_dt computes, by the
+ * same kernels.  U: device, nvar * ncells float64.  Enqueued on the context's
+ * stream; nothing is copied to the host and the call does not synchronise
+ * (kfvm_stats' min_rho / min_p are not updated).  A non-admissible cell raises
+ * the sticky KFVM_ERR_NONPHYSICAL word (kfvm_status), as kfvm_cfl_dt does.
+ * Scratch: the reduction's 1024 per-block partials (3 float64 each) sit in a
+ * library-wide device array of 24 KiB, one per GPU, held until the process
+ * ends; any grid size fits, since the reduction strides over the grid.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (other
+ * streams, other threads) race.  Errors: KFVM_ERR_STATE (null context),
+ * KFVM_ERR_ARG (null pointer, cfl <= 0), KFVM_ERR_HIP (launch). */
+int kfvm_cfl_dt_noalloc(kfvm_ctx *ctx, const double *U, double cfl, double *out_dev);
+
 /* Queue subsequent work on this HIP stream (hipStream_t passed as void*). */
 int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
 

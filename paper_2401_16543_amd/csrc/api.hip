@@ -26,6 +26,7 @@ struct kfvm_ctx {
     kfvm::Work work{};
     double *d_dt = nullptr;
     double min_rho = NAN, min_p = NAN;       // of the state of the last kfvm_cfl_dt
+    double *cfl_scratch = nullptr;           // device address of the static CFL scratch on this context's GPU
     std::vector<void *> allocs;
     std::string msg;
     // per-kernel timing (kfvm_set_timing): event pairs per launch, summed on query
@@ -300,7 +301,7 @@ static int init_context(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double
     A((void **)&c->work.fbar, sizeof(double) * (size_t)dim * nv * ncell);
     A((void **)&c->work.stage[0], sizeof(double) * (size_t)nv * ncell);
     A((void **)&c->work.stage[1], sizeof(double) * (size_t)nv * ncell);
-    A((void **)&c->work.cfl_part, sizeof(double) * 3 * 1024);
+    A((void **)&c->work.cfl_part, sizeof(double) * kfvm::CFL_SCRATCH_DOUBLES);
     A((void **)&c->work.err, sizeof(int) * 4);
     A((void **)&c->work.counts, sizeof(unsigned long long) * 2);
     A((void **)&c->d_dt, sizeof(double) * 3);
@@ -335,6 +336,8 @@ static int init_context(kfvm_ctx **out, const kfvm_mesh *mesh, int order, double
         e = hipMemcpy(c->d_wch, wch.data(), sizeof(double) * wch.size(), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemset(c->work.err, 0, sizeof(int) * 4);
+    // the allocation-free CFL call's scratch on this GPU (looked up once per device)
+    if (e == hipSuccess) e = kfvm::cfl_scratch_address(&c->cfl_scratch);
     if (e != hipSuccess) {
         hip_fail(nullptr, e, "upload");
         kfvm_destroy(c);
@@ -579,6 +582,18 @@ int kfvm_cfl_dt(kfvm_ctx *c, const double *U, double cfl, double *dt_host)
     c->min_rho = r[1];
     c->min_p = r[2];
     return rc;
+}
+
+int kfvm_cfl_dt_noalloc(kfvm_ctx *c, const double *U, double cfl, double *out_dev)
+{
+    if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
+    if (!U || !out_dev) return fail(c, KFVM_ERR_ARG, "null pointer");
+    if (!(cfl > 0.0)) return fail(c, KFVM_ERR_ARG, "cfl must be positive");
+    if (!c->cfl_scratch) return fail(c, KFVM_ERR_STATE, "no CFL scratch on this device");
+    const hipError_t e = kfvm::launch_cfl_scratch(c->dim, c->geom, c->cfl_scratch, c->work.err, U, cfl, out_dev,
+                                                  c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launch");
+    return KFVM_OK;
 }
 
 int kfvm_set_stream(kfvm_ctx *c, void *s)

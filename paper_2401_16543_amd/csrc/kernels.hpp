@@ -108,6 +108,16 @@ hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, co
                               const double *U, double *states, hipStream_t s);
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s);
+// The same reduction with its per-block partials in the library's static
+// device array (rhs_fp64.hip): cfl_scratch_address gives that array's address
+// on the current device (looked up once per device), which launch_cfl_scratch
+// takes as scratch_dev.  No allocation.
+constexpr int CFL_PARTS = 1024;                    // per-block partials of the CFL reduction
+constexpr int CFL_SCRATCH_DOUBLES = 3 * CFL_PARTS;
+constexpr int MAX_DEVICES = 64;
+hipError_t cfl_scratch_address(double **ptr);
+hipError_t launch_cfl_scratch(int dim, const Geom &g, double *scratch_dev, int *err, const double *U, double cfl,
+                              double *out_dev, hipStream_t s);
 // SSP(4,3,2): *out = root mean square over M values of (Up - (2 U3 - U)) /
 // (atol + rtol max(|U|, |Up|)); part: at least 1024 doubles of scratch.
 hipError_t launch_ssp_error(const double *U, const double *U3, const double *Up, long M, double atol, double rtol,

@@ -24,6 +24,7 @@
 // coalesced along x.  Blocks are remapped so that each XCD owns a contiguous
 // run of tiles, which keeps halo re-reads in that XCD's L2.
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.hpp"
 
@@ -908,16 +909,57 @@ hipError_t launch_face_states(int dim, int R, const Geom &g, const Tables &t, co
     return hipErrorInvalidValue;
 }
 
+static hipError_t cfl_launch(int dim, const Geom &g, double *part, int *err, const double *U, double cfl,
+                             double *dt_dev, hipStream_t s)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_cfl_partial<2>), dim3(CFL_PARTS), dim3(256), 0, s, U, part, err, g);
+    else
+        hipLaunchKernelGGL((k_cfl_partial<3>), dim3(CFL_PARTS), dim3(256), 0, s, U, part, err, g);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, s, part, CFL_PARTS, cfl, dt_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_cfl(int dim, const Geom &g, const Work &w, const double *U, double cfl, double *dt_dev,
                       hipStream_t s)
 {
-    const int nparts = 1024;
-    if (dim == 2)
-        hipLaunchKernelGGL((k_cfl_partial<2>), dim3(nparts), dim3(256), 0, s, U, w.cfl_part, w.err, g);
-    else
-        hipLaunchKernelGGL((k_cfl_partial<3>), dim3(nparts), dim3(256), 0, s, U, w.cfl_part, w.err, g);
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, s, w.cfl_part, nparts, cfl, dt_dev);
-    return hipGetLastError();
+    return cfl_launch(dim, g, w.cfl_part, w.err, U, cfl, dt_dev, s);
+}
+
+// ---------------------------------------------- allocation-free CFL reduction ---
+// The per-block partials of the allocation-free CFL call live in this
+// file-scope device array rather than in context memory: every GPU that loads
+// the library holds its own copy until the process ends, and every call on
+// that GPU shares it.  Each call overwrites all 3 x CFL_PARTS entries before
+// reading any, so nothing needs clearing; calls that overlap on one GPU race.
+// In host code the array's name is only a stand-in: kernels are given the
+// device address that cfl_scratch_address looks up once per device.
+static __device__ __align__(256) double scratch[CFL_SCRATCH_DOUBLES];
+
+hipError_t cfl_scratch_address(double **ptr)
+{
+    static std::mutex mu;
+    static double *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_cfl_scratch(int dim, const Geom &g, double *scratch_dev, int *err, const double *U, double cfl,
+                              double *out_dev, hipStream_t s)
+{
+    static_assert(3 * CFL_PARTS <= CFL_SCRATCH_DOUBLES, "the partials must fit the scratch array");
+    return cfl_launch(dim, g, scratch_dev, err, U, cfl, out_dev, s);
 }
 
 }  // namespace kfvm

@@ -24,7 +24,7 @@ EXPORTED = [
     "kfvm_face_states", "kfvm_weights_build", "kfvm_weights_size", "kfvm_last_error", "kfvm_destroy",
     "kfvm_set_timing", "kfvm_kernel_times", "kfvm_set_flags", "kfvm_mlp_sizes", "kfvm_set_gate",
     "kfvm_get_flags", "kfvm_gate_samples", "kfvm_mlp_train_step", "kfvm_set_indicator", "kfvm_kxrcf",
-    "kfvm_set_boundary", "kfvm_step_ssp432",
+    "kfvm_set_boundary", "kfvm_step_ssp432", "kfvm_cfl_dt_noalloc",
 ]
 KERNEL_CLASSES = ("recon", "flux", "update", "indicator")
 KFVM_IND_NONE, KFVM_IND_KXRCF = 0, 1
@@ -72,6 +72,7 @@ def load_library(path: str = _LIB_PATH):
         "kfvm_rhs": ([vp, vp, vp], ip),
         "kfvm_step": ([vp, vp, C.c_double], ip),
         "kfvm_cfl_dt": ([vp, vp, C.c_double, dp], ip),
+        "kfvm_cfl_dt_noalloc": ([vp, vp, C.c_double, vp], ip),
         "kfvm_set_stream": ([vp, vp], ip),
         "kfvm_set_precision": ([vp, ip], ip),
         "kfvm_set_limiter": ([vp, ip, C.c_double], ip),
@@ -233,6 +234,15 @@ class KFVM:
         dt = C.c_double()
         self._check(self.lib.kfvm_cfl_dt(self._h, self._state(U), float(cfl), C.byref(dt)))
         return dt.value
+
+    def cfl_dt_noalloc(self, U, cfl: float, out):
+        """kfvm_cfl_dt_noalloc: out (float64, 3 elements, on the GPU) receives dt,
+        the least density and the least pressure; asynchronous, allocates nothing."""
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != 3:
+            raise ValueError("out must be a contiguous float64 CUDA tensor of 3 elements")
+        self._stream()
+        self._check(self.lib.kfvm_cfl_dt_noalloc(self._h, self._state(U), float(cfl), C.c_void_p(out.data_ptr())))
+        return out
 
     def face_states(self, U):
         npts = 2 * self.dim * self.R ** (self.dim - 1)
