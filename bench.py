@@ -225,6 +225,12 @@ def main():
     print(f"# {args.mixed} + learned gate: {t_mix / args.steps * 1e3:.2f} ms/step, flagged {flagged:.4f}",
           file=sys.stderr, flush=True)
     l1 = float((U_mix[0] - U_plain[0]).abs().mean())
+    # the same decisions replayed on the FP64 path: the precision part of l1
+    from paper_2401_16543_amd.accuracy import replay_l1
+    plain = kfvm.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
+    l1_same, _ = replay_l1(dev, plain, U0, [dt] * args.steps)
+    plain.close()
+    print(f"# gated, same decisions replayed in FP64: L1 rho {l1_same:.3e}", file=sys.stderr, flush=True)
 
     def roof(kt):
         ms, nl = kt["recon"]
@@ -267,9 +273,11 @@ def main():
         "gate_flagged_fraction": flagged,
         "l1_rho_vs_fp64": l1,
         "l1_rho_vs_fp64_ungated": l1_ung,
+        "l1_rho_vs_fp64_same_decisions": l1_same,
         "l1_note": f"mean |rho - rho_fp64| after {args.steps} steps from the same state and dt (the FP64 GPU "
-                   f"path matches the CPU oracle to ~1e-15); ungated = split precision with WENO-AO everywhere, "
-                   f"so the gap between the two is the gate-induced difference",
+                   f"path matches the CPU oracle to ~1e-15); ungated = split precision with WENO-AO everywhere; "
+                   f"same_decisions = the gated run against the FP64 path replaying its decisions at every "
+                   f"stage (the precision error alone); l1_rho_vs_fp64 - that = the gate-induced difference",
         "roofline": {"kernel": "k_recon_mixed", "bound": "mfma", "achieved": cflops * ncell / mix_avg / 1e12,
                      "peak": MFMA_F16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": cflops * ncell / mix_avg / 1e12 / MFMA_F16_PEAK_TFLOPS,

@@ -35,6 +35,34 @@ PLANS = {
 }
 
 
+def replay_l1(gated, plain, U0, dts):
+    """L1 density difference between a gated run and the FP64 path replaying its
+    decisions: both advance SSP-RK3 stage by stage from U0 with the step sizes
+    dts; at every stage the gated context reconstructs its own state and decides,
+    and the FP64 context (`plain`, no gate) takes those decisions for its own
+    state (kfvm_set_flags).  The difference is then the precision error alone,
+    the scheme change of the decisions excluded.  The stage combinations are
+    the three Shu-Osher stages written out; `plain` has its flags cleared on
+    return.  Returns (L1 of rho, the gated run's final state)."""
+    Ug, Uf = U0.clone(), U0.clone()
+    for dt in dts:
+        Lg = gated.rhs(Ug)
+        plain.set_flags(gated.get_flags())
+        Lf = plain.rhs(Uf)
+        G1, F1 = Ug + dt * Lg, Uf + dt * Lf
+        Lg = gated.rhs(G1)
+        plain.set_flags(gated.get_flags())
+        Lf = plain.rhs(F1)
+        G2, F2 = 0.75 * Ug + 0.25 * (G1 + dt * Lg), 0.75 * Uf + 0.25 * (F1 + dt * Lf)
+        Lg = gated.rhs(G2)
+        plain.set_flags(gated.get_flags())
+        Lf = plain.rhs(F2)
+        Ug = Ug / 3.0 + (2.0 / 3.0) * (G2 + dt * Lg)
+        Uf = Uf / 3.0 + (2.0 / 3.0) * (F2 + dt * Lf)
+    plain.set_flags(None)
+    return float((Ug[0] - Uf[0]).abs().mean()), Ug
+
+
 def _misclassification(dev, U, n_in):
     """(false-smooth rate, false-troubled rate, flagged fraction) of the gate's
     decisions on state U against the FP64 WENO-AO labels."""
