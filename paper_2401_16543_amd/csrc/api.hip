@@ -219,7 +219,9 @@ int prepare_mixed(kfvm_ctx *c, int mode)
 {
     if (c->mix_mode == mode) return KFVM_OK;
     // the kernels address the face buffer with 32-bit per-lane byte offsets
-    if (c->geom.ncell >= (1L << 30)) return fail(c, KFVM_ERR_ARG, "the split-precision path takes fewer than 2^30 cells");
+    // the reconstruction stores through 32-bit lane offsets of up to 20 bytes per cell
+    if (c->geom.ncell * 20 >= (1L << 32))
+        return fail(c, KFVM_ERR_ARG, "the split-precision path takes fewer than 2^32 / 20 cells");
     const bool bf16 = mode == KFVM_SPLIT_BF16;
     double wmax = 0.0;
     for (double x : c->host_tables) wmax = std::fmax(wmax, std::fabs(x));
@@ -234,7 +236,8 @@ int prepare_mixed(kfvm_ctx *c, int mode)
         int rc = alloc(c, (void **)&c->d_mix_full, full.size() * 2);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->d_mix_lin, lin.size() * 2);
         if (rc == KFVM_OK) rc = alloc(c, (void **)&c->work.inc32,
-                                      sizeof(float) * (size_t)npts_of(c->dim, c->R) * c->nvar * c->geom.ncell);
+                                      sizeof(float) * (size_t)kfvm::inc_points(npts_of(c->dim, c->R)) * c->nvar *
+                                          c->geom.ncell);
         if (rc != KFVM_OK) return rc;
     }
     HIP_TRY(c, hipMemcpy(c->d_mix_full, full.data(), full.size() * 2, hipMemcpyHostToDevice));

@@ -37,10 +37,21 @@ struct Work {
     const int *guard;  // optional: the update writes nothing while *guard != 0 (a step's last stage)
     unsigned long long *counts;  // [2] scratch of kfvm_stats: limiter cells, WENO (cell, var) pairs
     const uint8_t *flags_in;   // optional [nvar][ncell] gate decisions (1 = WENO)
-    float *inc32;      // [n_pts][nvar][ncell] blended increments w_s - W_c (split-precision path)
+    float *inc32;      // blended increments w_s - W_c (split-precision path), inc_index layout
     double *fbar_top;  // [dim][nvar][plane] fluxes through the upper boundary faces of non-periodic axes
     long plane;        // largest boundary plane (cells), the stride of fbar_top
 };
+
+// Layout of the split path's float32 face-point increments: points in groups of
+// eight, [point / 8][nvar][point % 8][ncell], so that points tau and tau + 4
+// (bit 2 of tau clear), which the two half-waves of a cell hold side by side,
+// lie 4 ncell floats apart.  inc_points: the allocated point count (n_pts
+// rounded up to whole groups).
+__host__ __device__ constexpr long inc_index(int tau, int v, int nvar, long ncell)
+{
+    return ((long)((tau >> 3) * nvar + v) * 8 + (tau & 7)) * ncell;
+}
+__host__ __device__ constexpr int inc_points(int npts) { return (npts + 7) / 8 * 8; }
 
 // index of a cell in the boundary plane of axis a: its other two coordinates, the lower axis fastest
 __host__ __device__ inline long plane_index(int a, int cx, int cy, int cz, const int *n)

@@ -194,10 +194,12 @@ __device__ __forceinline__ f16v mfma_bf16(uint4 a, uint4 b, f16v c)
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bh8, a), __builtin_bit_cast(bh8, b), c, 0, 0, 0);
 }
 
+// two floats to a BF16 pair (a in the low half), rounded to nearest even, by
+// one packed conversion
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
 {
-    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
-    return (uint32_t)__builtin_bit_cast(uint16_t, ha) | (uint32_t)__builtin_bit_cast(uint16_t, hb) << 16;
+    const f2v v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2v));
 }
 
 // 16 accumulator registers from vec[base + unit]: register j holds unit
@@ -282,10 +284,10 @@ __device__ __forceinline__ float gate_forward(const uint4 (&xb)[GateShape<D>::KS
     return pair_sum(part) + vec[96];
 }
 
-// Running bounds of a lane's stored face-point increments (all points of the
-// cell, seen by both half-waves) for the positivity limiter: least and largest
-// density increment, least pressure-row increment, and the sum over the
-// velocity rows of their largest square.
+// Running bounds of a cell's stored face-point increments for the positivity
+// limiter: least and largest density increment, least pressure-row increment,
+// and the sum over the velocity rows of their largest square.  Each half-wave
+// bounds the points it stores; settle_bounds merges the two.
 struct IncBounds {
     float rlo = INFINITY, rhi = -INFINITY, plo = INFINITY, v2 = 0.f;
 };
@@ -301,6 +303,43 @@ __device__ __forceinline__ void note_increment(IncBounds &b, float x, float &v2k
     } else {
         v2k = fmaxf(v2k, x * x);
     }
+}
+
+// Face point tau of a cell is stored, and enters the limiter's bounds, in the
+// half-wave hf = bit 2 of tau: in the S0-only layout the accumulator holds
+// point T0 in the lower half-wave and T0 + 4 in the upper (T0 with bit 2
+// clear), so each lane keeps what it computed; the blended layout takes the
+// point tiles in pairs (t even: bit 2 clear, t + 1: set) and one exchange per
+// target gives each half-wave the sums of its own tile.  The bounds are then
+// per lane, and settle_bounds merges the two halves of a cell.
+__device__ __forceinline__ int owner_half(int tau) { return (tau >> 2) & 1; }
+
+__device__ __forceinline__ void settle_bounds(IncBounds &b)
+{
+    b.rlo = pair_min(b.rlo);
+    b.rhi = pair_max(b.rhi);
+    b.plo = pair_min(b.plo);
+}
+
+// store the float32 increment of variable K at this lane's point of the pair
+// (tau_lo, tau_lo + 4), bit 2 of tau_lo clear: the lower half-wave stores
+// tau_lo, the upper tau_lo + 4, by one store (the lane offset lo4 holds the
+// cell's byte offset plus, in the upper half, the 16 ncell bytes between the
+// two points, inc_index)
+template <int NV, int K>
+__device__ __forceinline__ void store_point(float *inc, int tau_lo, long ncell, uint32_t lo4, float val)
+{
+    at4(inc, 4 * inc_index(tau_lo, K, NV, ncell), lo4) = val;
+}
+
+// the blended value of the lane's own tile of a pair from its partial sums p0
+// (tile t) and p1 (tile t + 1): the lower half adds the upper half's p0, the
+// upper half the lower half's p1 (in the order lower + upper)
+__device__ __forceinline__ float pair_blend(float p0, float p1, int hf)
+{
+    float lo, hi;
+    halves(hf ? p0 : p1, lo, hi);
+    return hf ? lo + p1 : p0 + hi;
 }
 
 template <int D, int R, int K, bool BF, bool GATE>
@@ -407,7 +446,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
         use_weno = logit > thr && amax > (double)wsc[K == 0 ? 0 : (K <= D ? 1 : 2)];
         if (active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     }
-    const uint32_t co4 = co * 4u;
+    const uint32_t lo4 = co * 4u + (uint32_t)hf * (uint32_t)(16 * ncell);
     float v2k = 0.f;
     if (__any(use_weno && active)) {
         // smoothness indicators: float32 sums of squares over this lane's four
@@ -454,28 +493,42 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
             if (!use_weno) cq = q == 0 ? 1.0 : 0.0;
             cm[i] = (float)cq;
         }
-        // blended face-point increments
+        // blended face-point increments, point tiles in pairs
 #pragma unroll
-        for (int t = 0; t < M::TP_END; ++t) {
-            f16v acc = {};
+        for (int t = 0; t < M::TP_END; t += 2) {
+            f16v acc0 = {}, acc1 = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const uint4 ah = As[((t * KS + ks) * 2 + 0) * 64 + lane];
                 const uint4 al = As[((t * KS + ks) * 2 + 1) * 64 + lane];
-                acc = mfma<BF>(ah, bh[ks], acc);
-                acc = mfma<BF>(ah, bl[ks], acc);
-                acc = mfma<BF>(al, bh[ks], acc);
+                acc0 = mfma<BF>(ah, bh[ks], acc0);
+                acc0 = mfma<BF>(ah, bl[ks], acc0);
+                acc0 = mfma<BF>(al, bh[ks], acc0);
+            }
+            if (t + 1 < M::TP_END) {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const uint4 ah = As[(((t + 1) * KS + ks) * 2 + 0) * 64 + lane];
+                    const uint4 al = As[(((t + 1) * KS + ks) * 2 + 1) * 64 + lane];
+                    acc1 = mfma<BF>(ah, bh[ks], acc1);
+                    acc1 = mfma<BF>(ah, bl[ks], acc1);
+                    acc1 = mfma<BF>(al, bh[ks], acc1);
+                }
             }
 #pragma unroll
             for (int gq = 0; gq < 4; ++gq) {
-                const int tau = 4 * t + gq;
-                if (tau < NPTS) {
-                    float part4 = 0.f;
+                if (4 * t + gq < NPTS) {
+                    float p0 = 0.f, p1 = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) part4 += cm[i] * acc[4 * gq + i];
-                    const float val = ldexpf(pair_sum(part4), ue);
-                    note_increment<D, K>(bnd, val, v2k);
-                    if ((tau & 1) == hf && active) at4(inc, 4 * ((long)tau * NV + K) * ncell, co4) = val;
+                    for (int i = 0; i < 4; ++i) {
+                        p0 += cm[i] * acc0[4 * gq + i];
+                        p1 += cm[i] * acc1[4 * gq + i];
+                    }
+                    const float val = ldexpf(pair_blend(p0, p1, hf), ue);
+                    if (4 * (t + hf) + gq < NPTS) {
+                        note_increment<D, K>(bnd, val, v2k);
+                        if (active) store_point<NV, K>(inc, 4 * t + gq, ncell, lo4, val);
+                    }
                 }
             }
         }
@@ -494,22 +547,19 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                // register j holds point T0 in the lower half-wave and T0 + 4 in
-                // the upper; both have the parity of T0, so the owner half-wave
-                // (tau & 1) of the blended path stores the two
+                // register j holds point T0 in the lower half-wave, T0 + 4 in the upper
                 const int T0 = 32 * t + 8 * (j / 4) + j % 4;
-                float vlo, vhi;
-                halves(ldexpf(acc[j], ue), vlo, vhi);
-                if (T0 < NPTS) note_increment<D, K>(bnd, vlo, v2k);
-                if (T0 + 4 < NPTS) note_increment<D, K>(bnd, vhi, v2k);
-                if (active && hf == (T0 & 1)) {
-                    if (T0 < NPTS) at4(inc, 4 * ((long)T0 * NV + K) * ncell, co4) = vlo;
-                    if (T0 + 4 < NPTS) at4(inc, 4 * ((long)(T0 + 4) * NV + K) * ncell, co4) = vhi;
+                if (T0 < NPTS) {
+                    const float val = ldexpf(acc[j], ue);
+                    if (T0 + 4 < NPTS || hf == 0) {
+                        note_increment<D, K>(bnd, val, v2k);
+                        if (active) store_point<NV, K>(inc, T0, ncell, lo4, val);
+                    }
                 }
             }
         }
     }
-    if constexpr (K >= 1 && K <= D) bnd.v2 += v2k;
+    if constexpr (K >= 1 && K <= D) bnd.v2 += pair_max(v2k);
 }
 
 template <int D, int R, bool BF, bool GATE, int... K>
@@ -642,12 +692,12 @@ __device__ __forceinline__ void limiter_factors(const double (*tile)[MCfg<D, R>:
     if (exact) {
         PhiInv<D> pi;
         pi.init(ref, gam);
-        // this lane's face points: tau with (tau & 1) == hf (the ones it stored)
+        // this lane's face points: tau with bit 2 equal to hf (the ones it stored)
 #pragma unroll 1
-        for (int tau = hf; tau < NPTS; tau += 2) {
+        for (int tau = 4 * hf; tau < NPTS; tau = (tau & 3) == 3 ? tau + 5 : tau + 1) {
             double w[NV], d[NV], u[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)tau * NV + v) * g.ncell + cell];
+            for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(tau, v, NV, g.ncell) + cell];
             pi.apply(w, d);
 #pragma unroll
             for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
@@ -732,6 +782,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
                                    ga.thr, ga.flags_out, wsc, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
+    settle_bounds(bnd);
     if (lim.on)
         limiter_factors<D, R>(tile, ptile, lc, hf, ref, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
     if (active && hf == 0) {
@@ -923,7 +974,7 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
     // gate decisions (dilated over the 3^3 block, gbits >= 0), else the flags, else WENO-AO
     const bool use_weno = gbits >= 0 ? ((gbits >> K) & 1) != 0 : (flags ? at4(flags, (long)K * ncell, co) != 0 : true);
     if (gbits >= 0 && active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
-    const uint32_t co4 = co * 4u;
+    const uint32_t lo4 = co * 4u + (uint32_t)hf * (uint32_t)(16 * ncell);
     float v2k = 0.f;
     const bool wave_weno = __any(use_weno && active);
     if (__syncthreads_or(wave_weno)) {
@@ -988,30 +1039,46 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
                     }
                 }
             } else {
-                // blended face-point increments of this phase's point tiles
+                // blended face-point increments of this phase's point tiles, in
+                // pairs (a phase holds an even number of tiles)
+                static_assert(SC::PH % 2 == 0, "point tiles are blended in pairs");
 #pragma unroll
-                for (int tt = 0; tt < SC::PH; ++tt) {
+                for (int tt = 0; tt < SC::PH; tt += 2) {
                     const int t = SC::PH * (p - SC::NPD) + tt;
                     if (t < M::TP_END) {
-                        f16v acc = {};
+                        f16v acc0 = {}, acc1 = {};
 #pragma unroll
                         for (int ks = 0; ks < KS; ++ks) {
                             const uint4 ah = As[((tt * KS + ks) * 2 + 0) * 64 + lane];
                             const uint4 al = As[((tt * KS + ks) * 2 + 1) * 64 + lane];
-                            acc = mfma<BF>(ah, bh[ks], acc);
-                            acc = mfma<BF>(ah, bl[ks], acc);
-                            acc = mfma<BF>(al, bh[ks], acc);
+                            acc0 = mfma<BF>(ah, bh[ks], acc0);
+                            acc0 = mfma<BF>(ah, bl[ks], acc0);
+                            acc0 = mfma<BF>(al, bh[ks], acc0);
+                        }
+                        if (t + 1 < M::TP_END) {
+#pragma unroll
+                            for (int ks = 0; ks < KS; ++ks) {
+                                const uint4 ah = As[(((tt + 1) * KS + ks) * 2 + 0) * 64 + lane];
+                                const uint4 al = As[(((tt + 1) * KS + ks) * 2 + 1) * 64 + lane];
+                                acc1 = mfma<BF>(ah, bh[ks], acc1);
+                                acc1 = mfma<BF>(ah, bl[ks], acc1);
+                                acc1 = mfma<BF>(al, bh[ks], acc1);
+                            }
                         }
 #pragma unroll
                         for (int gq = 0; gq < 4; ++gq) {
-                            const int tau = 4 * t + gq;
-                            if (tau < NPTS) {
-                                float part4 = 0.f;
+                            if (4 * t + gq < NPTS) {
+                                float p0 = 0.f, p1 = 0.f;
 #pragma unroll
-                                for (int i = 0; i < 4; ++i) part4 += cm[i] * acc[4 * gq + i];
-                                const float val = ldexpf(pair_sum(part4), ue);
-                                note_increment<D, K>(bnd, val, v2k);
-                                if ((tau & 1) == hf && active) at4(inc, 4 * ((long)tau * NV + K) * ncell, co4) = val;
+                                for (int i = 0; i < 4; ++i) {
+                                    p0 += cm[i] * acc0[4 * gq + i];
+                                    p1 += cm[i] * acc1[4 * gq + i];
+                                }
+                                const float val = ldexpf(pair_blend(p0, p1, hf), ue);
+                                if (4 * (t + hf) + gq < NPTS) {
+                                    note_increment<D, K>(bnd, val, v2k);
+                                    if (active) store_point<NV, K>(inc, 4 * t + gq, ncell, lo4, val);
+                                }
                             }
                         }
                     }
@@ -1036,21 +1103,21 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
+                // register j holds point T0 in the lower half-wave, T0 + 4 in the upper
                 const int T0 = 32 * t + 8 * (j / 4) + j % 4;
-                float vlo, vhi;
-                halves(ldexpf(acc[j], ue), vlo, vhi);
-                if (T0 < NPTS) note_increment<D, K>(bnd, vlo, v2k);
-                if (T0 + 4 < NPTS) note_increment<D, K>(bnd, vhi, v2k);
-                if (active && hf == (T0 & 1)) {
-                    if (T0 < NPTS) at4(inc, 4 * ((long)T0 * NV + K) * ncell, co4) = vlo;
-                    if (T0 + 4 < NPTS) at4(inc, 4 * ((long)(T0 + 4) * NV + K) * ncell, co4) = vhi;
+                if (T0 < NPTS) {
+                    const float val = ldexpf(acc[j], ue);
+                    if (T0 + 4 < NPTS || hf == 0) {
+                        note_increment<D, K>(bnd, val, v2k);
+                        if (active) store_point<NV, K>(inc, T0, ncell, lo4, val);
+                    }
                 }
             }
         }
     }
     // the buffers are free again only when every wave is done with them
     __syncthreads();
-    if constexpr (K >= 1 && K <= D) bnd.v2 += v2k;
+    if constexpr (K >= 1 && K <= D) bnd.v2 += pair_max(v2k);
 }
 
 template <int D, int R, bool BF, int... K>
@@ -1141,6 +1208,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
                                     g.ncell, active && ok, sw, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
+    settle_bounds(bnd);
     if (lim.on)
         limiter_factors<D, R>(tile, ptile, lc, hf, ref, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
     if (active && hf == 0) {
@@ -1170,11 +1238,10 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
 #pragma unroll 1
     for (int gi = 0; gi < NG; ++gi) {
         double wL[NV], wR[NV], dL[NV], dR[NV], uL[NV], uR[NV], F[NV];
-        const long sL = (long)((2 * A + 1) * NG + gi) * NV * g.ncell, sR = (long)((2 * A + 0) * NG + gi) * NV * g.ncell;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            wL[v] = (double)incL[sL + v * g.ncell];
-            wR[v] = (double)incR[sR + v * g.ncell];
+            wL[v] = (double)incL[inc_index((2 * A + 1) * NG + gi, v, NV, g.ncell)];
+            wR[v] = (double)incR[inc_index((2 * A + 0) * NG + gi, v, NV, g.ncell)];
         }
         piL.apply(wL, dL);
         piR.apply(wR, dR);
@@ -1203,9 +1270,8 @@ __device__ __forceinline__ void boundary_face_flux_mixed(const float *__restrict
 #pragma unroll 1
     for (int gi = 0; gi < NG; ++gi) {
         double w[NV], d[NV], in[NV], out[NV], F[NV];
-        const long s = (long)((2 * A + side) * NG + gi) * NV * g.ncell;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) w[v] = (double)incc[s + v * g.ncell];
+        for (int v = 0; v < NV; ++v) w[v] = (double)incc[inc_index((2 * A + side) * NG + gi, v, NV, g.ncell)];
         pi.apply(w, d);
 #pragma unroll
         for (int v = 0; v < NV; ++v) in[v] = ref[v] + th * d[v];
@@ -1293,7 +1359,7 @@ __global__ __launch_bounds__(256) void k_states_mixed(const double *__restrict__
     for (int s = 0; s < NPTS; ++s) {
         double w[NV], d[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) w[v] = (double)inc[((long)s * NV + v) * g.ncell + cell];
+        for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(s, v, NV, g.ncell) + cell];
         pi.apply(w, d);
 #pragma unroll
         for (int v = 0; v < NV; ++v) states[(cell * NPTS + s) * NV + v] = ref[v] + th * d[v];
