@@ -59,6 +59,33 @@ def test_table1_isentropic_vortex(K, R, ns, band):
     assert all(e > 2.5 for e in eoc)
 
 
+@pytest.mark.xfail(strict=False, reason="the linear R = 3 S0 operator has a growing Fourier mode (odd in the "
+                   "transverse index, about 0.19/Delta for flow along an axis; test_oracle_weights pins it): at "
+                   "256^2 it lifts the t = 20 error to ~4e-6 against the printed 1.76e-8; cause not found")
+def test_table1_r3_256(K):
+    """Table 1's R = 3 entry at 256^2, kept apart from the parametrised rows."""
+    rows = np.loadtxt(__file__.rsplit("/", 1)[0] + "/golden/table1_isentropic_vortex.txt")
+    ref = rows[list(rows[:, 0]).index(256), 2]
+    err, res = _vortex_error(K, 3, 256, 1e-9)
+    say(f"case table1 R=3 n=256: L1 {err:.3e}, paper {ref:.3e} (x{err / ref:.3f}), {res['accepted']} steps")
+    assert abs(err / ref - 1.0) <= 0.20
+
+
+def test_gated_r3_vortex_two_periods_bounded(K):
+    """Long-run check of the gated R = 3 path, which runs the linear S0
+    reconstruction wherever the gate says smooth: the vortex at 256^2, where
+    the linear R = 3 scheme's growing mode takes the error up tenfold every two
+    time units from t ~ 14, over two periods (t = 40).  The gated error after
+    the second period stays within three times its error after the first (an
+    error that grows with time, not exponentially)."""
+    from paper_2401_16543_amd import vortex
+    out = vortex.run(R=3, ns=(256,), scheme="gate", tol=1e-6, precision="split_f16", periods=1)["results"][0]
+    out2 = vortex.run(R=3, ns=(256,), scheme="gate", tol=1e-6, precision="split_f16", periods=2)["results"][0]
+    say(f"case gated R=3 vortex n=256: L1 after one period {out['l1_rho']:.3e} ({out['accepted']} steps), "
+        f"after two {out2['l1_rho']:.3e} ({out2['accepted']} steps), WENO-AO on {out2['weno_fraction']:.4f}")
+    assert math.isfinite(out2["l1_rho"]) and out2["l1_rho"] <= 3.0 * out["l1_rho"]
+
+
 def test_vortex_driver(K):
     """The command-line driver of the study: the linear scheme reproduces the
     table's R = 2 errors at 32^2 and 64^2 on the FP64 path and on both split
