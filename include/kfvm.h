@@ -183,8 +183,8 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
  * KFVM_FP64 (default), or split hi/lo half-precision operands on the matrix
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
  * nonlinear-weight normalisation, the limiter, the Riemann solver and the
- * Runge-Kutta update stay in float64.  The split modes need fewer than
- * 2^32 / 20 (about 2.1e8) cells (KFVM_ERR_ARG otherwise). */
+ * Runge-Kutta update stay in float64.  The split modes need fewer than 2^27
+ * (about 1.3e8, a 512^3 grid) cells (KFVM_ERR_ARG otherwise). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 
 /* Boundary conditions of one axis (section 5.3: ghost cells filled by them,

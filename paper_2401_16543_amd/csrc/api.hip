@@ -219,9 +219,8 @@ int prepare_mixed(kfvm_ctx *c, int mode)
 {
     if (c->mix_mode == mode) return KFVM_OK;
     // the kernels address the face buffer with 32-bit per-lane byte offsets
-    // the reconstruction stores through 32-bit lane offsets of up to 20 bytes per cell
-    if (c->geom.ncell * 20 >= (1L << 32))
-        return fail(c, KFVM_ERR_ARG, "the split-precision path takes fewer than 2^32 / 20 cells");
+    // the reconstruction stores through 32-bit lane offsets of up to 32 bytes per cell
+    if (c->geom.ncell >= (1L << 27)) return fail(c, KFVM_ERR_ARG, "the split-precision path takes fewer than 2^27 cells");
     const bool bf16 = mode == KFVM_SPLIT_BF16;
     double wmax = 0.0;
     for (double x : c->host_tables) wmax = std::fmax(wmax, std::fabs(x));

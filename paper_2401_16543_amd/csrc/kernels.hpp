@@ -43,13 +43,16 @@ struct Work {
 };
 
 // Layout of the split path's float32 face-point increments: points in groups of
-// eight, [point / 8][nvar][point % 8][ncell], so that points tau and tau + 4
-// (bit 2 of tau clear), which the two half-waves of a cell hold side by side,
-// lie 4 ncell floats apart.  inc_points: the allocated point count (n_pts
-// rounded up to whole groups).
+// four, each cell's group one 16-byte vector,
+// [point / 8][nvar][(point / 4) % 2][ncell][point % 4].  A half-wave holds a
+// cell's four consecutive points tau .. tau + 3 (tau a multiple of 4) and
+// writes them with one vector store; the other half-wave's group, tau + 4 when
+// bit 2 of tau is clear, lies 4 ncell floats away.  inc_index gives the offset
+// of (point, variable) for cell 0; cell c adds 4 c.  inc_points: the allocated
+// point count (n_pts rounded up to whole groups of eight).
 __host__ __device__ constexpr long inc_index(int tau, int v, int nvar, long ncell)
 {
-    return ((long)((tau >> 3) * nvar + v) * 8 + (tau & 7)) * ncell;
+    return ((long)((tau >> 3) * nvar + v) * 2 + ((tau >> 2) & 1)) * ncell * 4 + (tau & 3);
 }
 __host__ __device__ constexpr int inc_points(int npts) { return (npts + 7) / 8 * 8; }
 

@@ -321,15 +321,15 @@ __device__ __forceinline__ void settle_bounds(IncBounds &b)
     b.plo = pair_min(b.plo);
 }
 
-// store the float32 increment of variable K at this lane's point of the pair
-// (tau_lo, tau_lo + 4), bit 2 of tau_lo clear: the lower half-wave stores
-// tau_lo, the upper tau_lo + 4, by one store (the lane offset lo4 holds the
-// cell's byte offset plus, in the upper half, the 16 ncell bytes between the
-// two points, inc_index)
+// store the float32 increments of variable K at this lane's group of four
+// points, tau_lo .. tau_lo + 3 in the lower half-wave and tau_lo + 4 .. tau_lo + 7
+// in the upper (tau_lo a multiple of 8), as one vector: the lane offset lo16
+// holds the cell's 16-byte column plus, in the upper half, the 16 ncell bytes
+// between the two groups (inc_index)
 template <int NV, int K>
-__device__ __forceinline__ void store_point(float *inc, int tau_lo, long ncell, uint32_t lo4, float val)
+__device__ __forceinline__ void store_group(float *inc, int tau_lo, long ncell, uint32_t lo16, float4 val)
 {
-    at4(inc, 4 * inc_index(tau_lo, K, NV, ncell), lo4) = val;
+    at4(reinterpret_cast<float4 *>(inc), 4 * inc_index(tau_lo, K, NV, ncell), lo16) = val;
 }
 
 // the blended value of the lane's own tile of a pair from its partial sums p0
@@ -446,7 +446,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
         use_weno = logit > thr && amax > (double)wsc[K == 0 ? 0 : (K <= D ? 1 : 2)];
         if (active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     }
-    const uint32_t lo4 = co * 4u + (uint32_t)hf * (uint32_t)(16 * ncell);
+    const uint32_t lo16 = co * 16u + (uint32_t)hf * (uint32_t)(16 * ncell);
     float v2k = 0.f;
     if (__any(use_weno && active)) {
         // smoothness indicators: float32 sums of squares over this lane's four
@@ -515,6 +515,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                     acc1 = mfma<BF>(al, bh[ks], acc1);
                 }
             }
+            float grp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int gq = 0; gq < 4; ++gq) {
                 if (4 * t + gq < NPTS) {
@@ -524,13 +525,11 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                         p0 += cm[i] * acc0[4 * gq + i];
                         p1 += cm[i] * acc1[4 * gq + i];
                     }
-                    const float val = ldexpf(pair_blend(p0, p1, hf), ue);
-                    if (4 * (t + hf) + gq < NPTS) {
-                        note_increment<D, K>(bnd, val, v2k);
-                        if (active) store_point<NV, K>(inc, 4 * t + gq, ncell, lo4, val);
-                    }
+                    grp[gq] = ldexpf(pair_blend(p0, p1, hf), ue);
+                    if (4 * (t + hf) + gq < NPTS) note_increment<D, K>(bnd, grp[gq], v2k);
                 }
             }
+            if (active) store_group<NV, K>(inc, 4 * t, ncell, lo16, make_float4(grp[0], grp[1], grp[2], grp[3]));
         }
     } else {
         // every cell of the wave is linear for this variable: S0 face rows only
@@ -546,15 +545,18 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                 acc = mfma<BF>(al, bh[ks], acc);
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                // register j holds point T0 in the lower half-wave, T0 + 4 in the upper
-                const int T0 = 32 * t + 8 * (j / 4) + j % 4;
+            for (int G = 0; G < 4; ++G) {
+                // registers 4 G .. 4 G + 3 hold points T0 .. T0 + 3 in the lower
+                // half-wave, T0 + 4 .. T0 + 7 in the upper
+                const int T0 = 32 * t + 8 * G;
                 if (T0 < NPTS) {
-                    const float val = ldexpf(acc[j], ue);
-                    if (T0 + 4 < NPTS || hf == 0) {
-                        note_increment<D, K>(bnd, val, v2k);
-                        if (active) store_point<NV, K>(inc, T0, ncell, lo4, val);
+                    float grp[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        grp[i] = ldexpf(acc[4 * G + i], ue);
+                        if (T0 + i + 4 < NPTS || (hf == 0 && T0 + i < NPTS)) note_increment<D, K>(bnd, grp[i], v2k);
                     }
+                    if (active) store_group<NV, K>(inc, T0, ncell, lo16, make_float4(grp[0], grp[1], grp[2], grp[3]));
                 }
             }
         }
@@ -697,7 +699,7 @@ __device__ __forceinline__ void limiter_factors(const double (*tile)[MCfg<D, R>:
         for (int tau = 4 * hf; tau < NPTS; tau = (tau & 3) == 3 ? tau + 5 : tau + 1) {
             double w[NV], d[NV], u[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(tau, v, NV, g.ncell) + cell];
+            for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(tau, v, NV, g.ncell) + 4 * cell];
             pi.apply(w, d);
 #pragma unroll
             for (int v = 0; v < NV; ++v) u[v] = ref[v] + th_rho * d[v];
@@ -974,7 +976,7 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
     // gate decisions (dilated over the 3^3 block, gbits >= 0), else the flags, else WENO-AO
     const bool use_weno = gbits >= 0 ? ((gbits >> K) & 1) != 0 : (flags ? at4(flags, (long)K * ncell, co) != 0 : true);
     if (gbits >= 0 && active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
-    const uint32_t lo4 = co * 4u + (uint32_t)hf * (uint32_t)(16 * ncell);
+    const uint32_t lo16 = co * 16u + (uint32_t)hf * (uint32_t)(16 * ncell);
     float v2k = 0.f;
     const bool wave_weno = __any(use_weno && active);
     if (__syncthreads_or(wave_weno)) {
@@ -1065,6 +1067,7 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
                                 acc1 = mfma<BF>(al, bh[ks], acc1);
                             }
                         }
+                        float grp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int gq = 0; gq < 4; ++gq) {
                             if (4 * t + gq < NPTS) {
@@ -1074,13 +1077,12 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
                                     p0 += cm[i] * acc0[4 * gq + i];
                                     p1 += cm[i] * acc1[4 * gq + i];
                                 }
-                                const float val = ldexpf(pair_blend(p0, p1, hf), ue);
-                                if (4 * (t + hf) + gq < NPTS) {
-                                    note_increment<D, K>(bnd, val, v2k);
-                                    if (active) store_point<NV, K>(inc, 4 * t + gq, ncell, lo4, val);
-                                }
+                                grp[gq] = ldexpf(pair_blend(p0, p1, hf), ue);
+                                if (4 * (t + hf) + gq < NPTS) note_increment<D, K>(bnd, grp[gq], v2k);
                             }
                         }
+                        if (active)
+                            store_group<NV, K>(inc, 4 * t, ncell, lo16, make_float4(grp[0], grp[1], grp[2], grp[3]));
                     }
                 }
             }
@@ -1102,15 +1104,18 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
                 acc = mfma<BF>(al, bh[ks], acc);
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                // register j holds point T0 in the lower half-wave, T0 + 4 in the upper
-                const int T0 = 32 * t + 8 * (j / 4) + j % 4;
+            for (int G = 0; G < 4; ++G) {
+                // registers 4 G .. 4 G + 3 hold points T0 .. T0 + 3 in the lower
+                // half-wave, T0 + 4 .. T0 + 7 in the upper
+                const int T0 = 32 * t + 8 * G;
                 if (T0 < NPTS) {
-                    const float val = ldexpf(acc[j], ue);
-                    if (T0 + 4 < NPTS || hf == 0) {
-                        note_increment<D, K>(bnd, val, v2k);
-                        if (active) store_point<NV, K>(inc, T0, ncell, lo4, val);
+                    float grp[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        grp[i] = ldexpf(acc[4 * G + i], ue);
+                        if (T0 + i + 4 < NPTS || (hf == 0 && T0 + i < NPTS)) note_increment<D, K>(bnd, grp[i], v2k);
                     }
+                    if (active) store_group<NV, K>(inc, T0, ncell, lo16, make_float4(grp[0], grp[1], grp[2], grp[3]));
                 }
             }
         }
@@ -1232,16 +1237,34 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
     const double thL = theta[lower] * theta[g.ncell + lower];
     PhiInv<D> piL;
     piL.init(refL, g.gamma);
-    const float *incL = inc + lower, *incR = inc + cell;
+    const float *incL = inc + 4 * lower, *incR = inc + 4 * cell;
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
-#pragma unroll 1
+    // four Gauss points per face (3D R = 2): each side's face is one vector per
+    // variable, loaded at once (the loop is unrolled: the vectors' lanes are
+    // compile-time indices)
+    constexpr bool VEC = NG == 4;
+    float4 gL[VEC ? NV : 1], gR[VEC ? NV : 1];
+    if constexpr (VEC) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            gL[v] = *reinterpret_cast<const float4 *>(incL + inc_index((2 * A + 1) * NG, v, NV, g.ncell));
+            gR[v] = *reinterpret_cast<const float4 *>(incR + inc_index((2 * A + 0) * NG, v, NV, g.ncell));
+        }
+    }
+    constexpr int UNROLL = VEC ? NG : 1;
+#pragma unroll UNROLL
     for (int gi = 0; gi < NG; ++gi) {
         double wL[NV], wR[NV], dL[NV], dR[NV], uL[NV], uR[NV], F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            wL[v] = (double)incL[inc_index((2 * A + 1) * NG + gi, v, NV, g.ncell)];
-            wR[v] = (double)incR[inc_index((2 * A + 0) * NG + gi, v, NV, g.ncell)];
+            if constexpr (VEC) {
+                wL[v] = (double)gL[v][gi];
+                wR[v] = (double)gR[v][gi];
+            } else {
+                wL[v] = (double)incL[inc_index((2 * A + 1) * NG + gi, v, NV, g.ncell)];
+                wR[v] = (double)incR[inc_index((2 * A + 0) * NG + gi, v, NV, g.ncell)];
+            }
         }
         piL.apply(wL, dL);
         piR.apply(wR, dR);
@@ -1264,7 +1287,7 @@ __device__ __forceinline__ void boundary_face_flux_mixed(const float *__restrict
 {
     using S = Stencil<D, R>;
     constexpr int NV = D + 2, NG = S::NG;
-    const float *incc = inc + cell;
+    const float *incc = inc + 4 * cell;
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fbar[v] = 0.0;
 #pragma unroll 1
@@ -1359,7 +1382,7 @@ __global__ __launch_bounds__(256) void k_states_mixed(const double *__restrict__
     for (int s = 0; s < NPTS; ++s) {
         double w[NV], d[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(s, v, NV, g.ncell) + cell];
+        for (int v = 0; v < NV; ++v) w[v] = (double)inc[inc_index(s, v, NV, g.ncell) + 4 * cell];
         pi.apply(w, d);
 #pragma unroll
         for (int v = 0; v < NV; ++v) states[(cell * NPTS + s) * NV + v] = ref[v] + th * d[v];

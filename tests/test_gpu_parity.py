@@ -274,3 +274,17 @@ def test_bad_arguments_are_rejected(K):
     U = _state("smooth", 2, 16, 1).cuda()
     rc = dev.lib.kfvm_rhs(dev._h, dev._state(U), dev._state(U))
     assert rc == K.KFVM_ERR_ARG
+
+
+def test_split_path_cell_limit(K):
+    """The split path stores through 32-bit lane offsets of up to 32 bytes per
+    cell: a grid of 2^27 cells is refused by kfvm_set_precision (the FP64 path
+    still takes it); one cell fewer along a row is accepted."""
+    say("case split-path cell limit")
+    dev = K.KFVM(2, (16384, 8192), order=5)
+    with pytest.raises(K.KfvmError):
+        dev.set_precision("split_f16")
+    dev.close()
+    dev = K.KFVM(2, (16383, 8192), order=5)
+    dev.set_precision("split_f16")
+    dev.close()
