@@ -356,7 +356,9 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
     const int hf = lane >> 5;
     const double Wc = w_component<D, K, C::HN>(tile, lc, ph);
 
-    // increments over this lane's slots 16 ks + 8 hf + i
+    // increments over this lane's slots 16 ks + 8 hf + i; the next k-step's
+    // LDS index waits for this one's values (empty asm), so at most one
+    // k-step's reads are in flight
     double dl[KS][8];
     double amax = 0.0;
     int lcc = lc;
@@ -365,7 +367,6 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             dl[ks][i] = slot_increment<D, R, K>(tile, lcc, hf, 16 * ks + i, 16 * ks + 8 + i, ph, Wc);
-            asm volatile("" : "+v"(dl[ks][i]));
             amax = fmax(amax, fabs(dl[ks][i]));
         }
         asm volatile("" : "+v"(lcc) : "v"(dl[ks][7]));
@@ -420,7 +421,6 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
                     const bool okw = hf ? (wB < 25) : (wA < 25);
                     const double w = w_component<D, K, C::HN>(tile, lg + (hf ? oB : oA), ph);
                     gw[ks][i] = okw ? w - Wc : 0.0;
-                    asm volatile("" : "+v"(gw[ks][i]));
                     gmax = fmax(gmax, fabs(gw[ks][i]));
                 }
                 asm volatile("" : "+v"(lg) : "v"(gw[ks][7]));
