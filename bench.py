@@ -225,6 +225,19 @@ def main():
     print(f"# {args.mixed} + learned gate: {t_mix / args.steps * 1e3:.2f} ms/step, flagged {flagged:.4f}",
           file=sys.stderr, flush=True)
     l1 = float((U_mix[0] - U_plain[0]).abs().mean())
+    # misclassification of the gate's decisions on the final state against the
+    # WENO-AO labels of the FP64 reconstruction (troubled iff 1 - omega_0/gamma_0 > cut)
+    dev.rhs(U_mix)
+    dec = dev.get_flags().bool()
+    _, ratio = dev.gate_samples(U_mix, inputs=False)
+    troubled = (1.0 - ratio) > gate_mod.LABEL_CUT
+    n_tr = int(troubled.sum())
+    mis = {"false_smooth": float((troubled & ~dec).sum()) / max(1, n_tr),
+           "false_troubled": float((~troubled & dec).sum()) / max(1, int((~troubled).sum())),
+           "labelled_troubled": n_tr / troubled.numel(), "flagged": float(dec.float().mean()),
+           "note": f"decisions of the gated run's last state against the labels of its FP64 WENO-AO "
+                   f"reconstruction (troubled iff 1 - omega_0/gamma_0 > {gate_mod.LABEL_CUT})"}
+    del dec, ratio, troubled
     # the same decisions replayed on the FP64 path: the precision part of l1
     from paper_2401_16543_amd.accuracy import replay_l1
     plain = kfvm.KFVM(d, (n,) * d, order=2 * R + 1, gamma=gamma)
@@ -271,6 +284,7 @@ def main():
                    "gate": f"learned ({gmeta['samples']} training samples, threshold {thr:.4f}, "
                            f"held-out false-smooth {gmeta['val_false_smooth']:.4f})"},
         "gate_flagged_fraction": flagged,
+        "gate_misclassification": mis,
         "l1_rho_vs_fp64": l1,
         "l1_rho_vs_fp64_ungated": l1_ung,
         "l1_rho_vs_fp64_same_decisions": l1_same,

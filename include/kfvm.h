@@ -326,7 +326,8 @@ int kfvm_get_flags(kfvm_ctx *ctx, uint8_t *flags);
 
 /* Training samples from state U: x[nvar][ncells][n_in] float32 gate inputs and
  * ratio[nvar][ncells] float32 = omega_0 / gamma_0 of the FP64 WENO-AO
- * reconstruction (eq. nlinWts; 1 where the variable is linear).  Device buffers. */
+ * reconstruction (eq. nlinWts; 1 where the variable is linear).  Device buffers;
+ * x may be NULL (the labels alone, e.g. to measure the gate's misclassification). */
 int kfvm_gate_samples(kfvm_ctx *ctx, const double *U, float *x, float *ratio);
 
 /* One training step on a batch of B samples x[B][n_in], labels y[B] in {0, 1}

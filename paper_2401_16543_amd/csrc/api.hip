@@ -868,10 +868,10 @@ int kfvm_get_flags(kfvm_ctx *c, uint8_t *flags)
 int kfvm_gate_samples(kfvm_ctx *c, const double *U, float *x, float *ratio)
 {
     if (!c) return fail(nullptr, KFVM_ERR_STATE, "null context");
-    if (!U || !x || !ratio) return fail(c, KFVM_ERR_ARG, "null buffer");
+    if (!U || !ratio) return fail(c, KFVM_ERR_ARG, "null buffer");
     const int rc = ensure_face64(c);
     if (rc != KFVM_OK) return rc;
-    hipError_t e = kfvm::launch_gate_inputs(c->dim, c->geom, U, x, c->stream);
+    hipError_t e = x ? kfvm::launch_gate_inputs(c->dim, c->geom, U, x, c->stream) : hipSuccess;
     kfvm::Tables t{c->d_tables, c->d_wch};
     if (e == hipSuccess) e = kfvm::launch_recon_ratio(c->dim, c->R, c->geom, t, c->work, c->lim, U, ratio, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "launch");

@@ -341,16 +341,17 @@ class KFVM:
         self._check(self.lib.kfvm_get_flags(self._h, C.c_void_p(out.data_ptr())))
         return out
 
-    def gate_samples(self, U):
-        """(x [nvar, ncell, n_in] float32, omega_0/gamma_0 [nvar, ncell] float32)."""
+    def gate_samples(self, U, inputs: bool = True):
+        """(x [nvar, ncell, n_in] float32 or None, omega_0/gamma_0 [nvar, ncell] float32);
+        inputs=False: the labels alone."""
         n_in, _ = self.mlp_sizes()
         ncell = 1
         for v in self.n:
             ncell *= v
-        x = torch.empty((self.nvar, ncell, n_in), dtype=torch.float32, device=U.device)
+        x = torch.empty((self.nvar, ncell, n_in), dtype=torch.float32, device=U.device) if inputs else None
         r = torch.empty((self.nvar, ncell), dtype=torch.float32, device=U.device)
         self._stream()
-        self._check(self.lib.kfvm_gate_samples(self._h, self._state(U), C.c_void_p(x.data_ptr()),
+        self._check(self.lib.kfvm_gate_samples(self._h, self._state(U), C.c_void_p(x.data_ptr()) if inputs else None,
                                                C.c_void_p(r.data_ptr())))
         return x, r
 

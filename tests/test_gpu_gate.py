@@ -158,6 +158,9 @@ def test_gate_samples_match_oracle(K, oracle_mod, d, n):
     say(f"  x max diff {ex:.2e}  ratio max diff {er:.2e}  troubled frac {(1 - r_ref > 0.5).mean():.3f}")
     assert ex <= 1e-6
     assert er <= 1e-5
+    # the labels alone (no input buffer): the same ratios
+    x2, r2 = dev.gate_samples(U.cuda(), inputs=False)
+    assert x2 is None and torch.equal(r2, r)
 
 
 @pytest.mark.parametrize("d,R,n", [(2, 2, 48), (2, 3, 48), (3, 2, 16)])
