@@ -148,11 +148,21 @@ __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uin
     using T2 = std::conditional_t<BF, b2v, h2v>;
     const f2v y = {ya, yb};
     const T2 h = __builtin_convertvector(y, T2);
-    const f2v hf = __builtin_convertvector(h, f2v);
-    const f2v r = {ya - hf.x, yb - hf.y};
-    const T2 l = __builtin_convertvector(r, T2);
     hi = __builtin_bit_cast(uint32_t, h);
-    lo = __builtin_bit_cast(uint32_t, l);
+    if constexpr (BF) {
+        const f2v hf = __builtin_convertvector(h, f2v);
+        const f2v r = {ya - hf.x, yb - hf.y};
+        lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, T2));
+    } else {
+        // the mixed-precision FMA reads each FP16 half of hi as an operand and
+        // rounds the float32 result y - hi (exact) once to FP16: the same
+        // residual as widening hi, subtracting and converting, in one
+        // instruction per value instead of two and a half
+        asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+            "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=&v"(lo)
+            : "v"(hi), "v"(ya), "v"(yb));
+    }
 }
 
 // increment of variable K at contraction slots kA (lower half-wave) and kB
@@ -218,22 +228,27 @@ __device__ __forceinline__ f16v unit_regs(const float *vec, int hf)
     return a;
 }
 
-// GELU of the inference by chords: bin k of width 1/64 on [-6, 6) holds
-// (a_k, b_k), the line through gelu_f at the bin's ends; below -6 and from 6 on
-// the end chords continue (GELU is 0 or z there to 1e-8).  The chords are
-// within 2.5e-5 of gelu_f, far below the BF16 rounding of the hidden layer, and
-// cost one LDS read and a few plain VALU operations against the exponential and
-// reciprocal of gelu_f, which the VALU-bound gated reconstruction feels.  The
-// table sits in LDS after the gate's vector parameters (GVEC_TAB floats on).
+// GELU of the inference by chords: bin k of width 1/64 centred on
+// z = (k - 384) / 64 (k = 0 .. 767, so the bins tile [-6 - 1/128, 6 - 1/128))
+// holds (a_k, b_k), the line through gelu_f at the bin's ends; beyond the first
+// and last bins their chords continue (GELU is 0 or z there to 1e-8).  The
+// chords are within 2.5e-5 of gelu_f, far below the BF16 rounding of the hidden
+// layer, and cost one LDS read and four plain VALU operations against the
+// exponential and reciprocal of gelu_f, which the VALU-bound gated
+// reconstruction feels.  The table sits in LDS after the gate's vector
+// parameters (GVEC_TAB floats on).
 constexpr int GELU_NB = 768;
 constexpr int GVEC_TAB = 104;                          // after b1, b2, w3, b3 (97 floats), 16-byte aligned
 constexpr int GVEC_SIZE = GVEC_TAB + 2 * GELU_NB;
+// 1.5 * 2^23: the floats of [2^23, 2^24) are the integers, so adding it rounds
+// to the nearest integer and leaves that integer in the low mantissa bits
+constexpr float GELU_MAGIC = 12582912.f;
 
 __device__ __forceinline__ void gelu_table_fill(float *gvec, int tid, int nt)
 {
     float2 *tab = reinterpret_cast<float2 *>(gvec + GVEC_TAB);
     for (int k = tid; k < GELU_NB; k += nt) {
-        const float z0 = -6.f + (float)k * (1.f / 64.f), z1 = z0 + 1.f / 64.f;
+        const float z0 = -6.f + ((float)k - 0.5f) * (1.f / 64.f), z1 = z0 + 1.f / 64.f;
         const float g0 = gelu_f(z0), g1 = gelu_f(z1);
         const float b = (g1 - g0) * 64.f;
         tab[k] = make_float2(g0 - b * z0, b);
@@ -243,8 +258,11 @@ __device__ __forceinline__ void gelu_table_fill(float *gvec, int tid, int nt)
 __device__ __forceinline__ float gelu_tab(float z, const float *gvec)
 {
     const float2 *tab = reinterpret_cast<const float2 *>(gvec + GVEC_TAB);
-    // bin index clamped in float (fmaxf of NaN gives 0, so it stays in range)
-    const int k = (int)fminf(fmaxf(fmaf(z, 64.f, 384.f), 0.f), (float)(GELU_NB - 1));
+    // bin k = the integer nearest 64 z + 384, formed by the magic add and
+    // clamped in float to [0, 767] (fmaxf of NaN gives the lower end, so any z
+    // stays in range); its bits less the magic's are k
+    const float t = fminf(fmaxf(fmaf(z, 64.f, 384.f + GELU_MAGIC), GELU_MAGIC), GELU_MAGIC + (float)(GELU_NB - 1));
+    const uint32_t k = __float_as_uint(t) - __float_as_uint(GELU_MAGIC);
     const float2 c = tab[k];
     return fmaf(c.y, z, c.x);
 }
@@ -266,14 +284,16 @@ __device__ __forceinline__ float gate_forward(const uint4 (&xb)[GateShape<D>::KS
         P[p] = pack_bf16(gelu_tab(acc[2 * p], vec), gelu_tab(acc[2 * p + 1], vec));
         asm volatile("" : "+v"(P[p]));
     }
-    // to the B layout (unit 16 ks + 8 hf + i): swap the pairs each half needs
-    uint32_t rv[4];
-    rv[0] = partner(hf ? P[0] : P[2], hf);
-    rv[1] = partner(hf ? P[1] : P[3], hf);
-    rv[2] = partner(hf ? P[4] : P[6], hf);
-    rv[3] = partner(hf ? P[5] : P[7], hf);
-    const uint4 b0 = hf ? make_uint4(rv[0], rv[1], P[2], P[3]) : make_uint4(P[0], P[1], rv[0], rv[1]);
-    const uint4 b1 = hf ? make_uint4(rv[2], rv[3], P[6], P[7]) : make_uint4(P[4], P[5], rv[2], rv[3]);
+    // to the B layout (unit 16 ks + 8 hf + i): P[p] holds units
+    // 8 (p / 2) + 4 hf + 2 (p % 2) and the next; one exchange of P[p] with
+    // P[p + 2] leaves the first register with units 16 ks + 8 hf + {0..3} and
+    // the second with 16 ks + 8 hf + {4..7} in both half-waves (ks = p / 4)
+    const auto s02 = __builtin_amdgcn_permlane32_swap(P[0], P[2], false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(P[1], P[3], false, false);
+    const auto s46 = __builtin_amdgcn_permlane32_swap(P[4], P[6], false, false);
+    const auto s57 = __builtin_amdgcn_permlane32_swap(P[5], P[7], false, false);
+    const uint4 b0 = make_uint4(s02[0], s13[0], s02[1], s13[1]);
+    const uint4 b1 = make_uint4(s46[0], s57[0], s46[1], s57[1]);
     f16v acc2 = unit_regs(vec + 32, hf);
     acc2 = mfma_bf16(Wg[(KSG + 0) * 64 + lane], b0, acc2);
     acc2 = mfma_bf16(Wg[(KSG + 1) * 64 + lane], b1, acc2);
@@ -578,56 +598,120 @@ __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::
 }
 
 // Tile of conserved averages plus its R-cell halo (the ghost fill: periodic
-// wrap, or the boundary conditions of non-periodic axes) into LDS; with the limiter on, also each tile cell's pressure (-1 where the
-// average is not admissible) for the neighbourhood bounds.
-template <int D, int R, int NTHR, typename PT>
-__device__ __forceinline__ void load_tile(const double *__restrict__ U, const Geom &g, const Limiter &lim, int x0,
-                                          int y0, int z0, double (*tile)[MCfg<D, R>::HN], PT *ptile)
-{
+// wrap, or the boundary conditions of non-periodic axes) into LDS; with the
+// limiter on, also each tile cell's pressure (-1 where the average is not
+// admissible) for the neighbourhood bounds.  In two phases: issue() puts every
+// global load of the thread in flight (its tile cells sit in registers), and
+// commit() writes them to LDS, so that a block's prologue waits for memory once
+// rather than once per strided pass.  A tile whose halo crosses a
+// non-periodic boundary fills its ghosts cell by cell in commit().
+template <int D, int R, int NTHR>
+struct TileLoad {
     using C = MCfg<D, R>;
-    constexpr int NV = C::NV;
-    const double gam = g.gamma;
-    // a single conditional wrap reaches every halo index once the grid is at
-    // least a tile plus R wide along each axis; smaller grids take the modulo
-    const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
-    // only a tile whose halo crosses a non-periodic boundary needs the ghost fill
+    static constexpr int NV = C::NV, NIT = (C::HN + NTHR - 1) / NTHR;
+    double u[NIT][NV];
     bool ghosts = false;
-    if (!g.periodic) {
-        const int o[3] = {x0, y0, z0}, h[3] = {C::HX, C::HY, C::HZ};
+
+    __device__ __forceinline__ void issue(const double *__restrict__ U, const Geom &g, int x0, int y0, int z0)
+    {
+        if (!g.periodic) {
+            const int o[3] = {x0, y0, z0}, h[3] = {C::HX, C::HY, C::HZ};
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-            ghosts = ghosts || (g.bc[a][0] != BC_PERIODIC && (o[a] < 0 || o[a] + h[a] > g.n[a]));
-    }
-    for (int i = threadIdx.x; i < C::HN; i += NTHR) {
-        const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
-        double u[NV];
-        if (ghosts) {
-            ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u);
+            for (int a = 0; a < D; ++a)
+                ghosts = ghosts || (g.bc[a][0] != BC_PERIODIC && (o[a] < 0 || o[a] + h[a] > g.n[a]));
+        }
+        if (ghosts) return;
+        // a single conditional wrap reaches every halo index once the grid is at
+        // least a tile plus R wide along each axis; smaller grids take the modulo
+        const bool near = g.n[0] >= C::TX + R && g.n[1] >= C::TY + R && (D == 2 || g.n[2] >= C::TZ + R);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) tile[v][i] = u[v];
-        } else {
+        for (int it = 0; it < NIT; ++it) {
+            // past the tile's end a thread reloads its last cell and stores nothing
+            const int i = min((int)threadIdx.x + it * NTHR, C::HN - 1);
+            const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
             const int gx = near ? wrapi(x0 + hx, g.n[0]) : wrap_any(x0 + hx, g.n[0]);
             const int gy = near ? wrapi(y0 + hy, g.n[1]) : wrap_any(y0 + hy, g.n[1]);
             const int gz = D == 3 ? (near ? wrapi(z0 + hz, g.n[2]) : wrap_any(z0 + hz, g.n[2])) : 0;
             const long cl = gx + (long)g.n[0] * (gy + (long)g.n[1] * gz);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                u[v] = U[v * g.ncell + cl];
-                tile[v][i] = u[v];
-            }
-        }
-        if (lim.on) {
-            double mm = 0.0;
-            bool fin = true;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) fin = fin && isfinite(u[v]);
-#pragma unroll
-            for (int a = 0; a < D; ++a) mm += u[1 + a] * u[1 + a];
-            const double p = (gam - 1.0) * (u[D + 1] - 0.5 * mm * rcp64(u[0]));
-            ptile[i] = (PT)(fin && u[0] > 0.0 && p > 0.0 ? p : -1.0);
+            for (int v = 0; v < NV; ++v) u[it][v] = U[v * g.ncell + cl];
         }
     }
+
+    template <typename PT>
+    __device__ __forceinline__ void commit(const double *__restrict__ U, const Geom &g, const Limiter &lim, int x0,
+                                           int y0, int z0, double (*tile)[C::HN], PT *ptile)
+    {
+        const double gam = g.gamma;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = (int)threadIdx.x + it * NTHR;
+            if (i >= C::HN) break;
+            if (ghosts) {
+                const int hx = i % C::HX, hy = (i / C::HX) % C::HY, hz = i / (C::HX * C::HY);
+                ghost_load<D>(U, g, x0 + hx, y0 + hy, D == 3 ? z0 + hz : 0, u[it]);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tile[v][i] = u[it][v];
+            if (lim.on) {
+                double mm = 0.0;
+                bool fin = true;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) fin = fin && isfinite(u[it][v]);
+#pragma unroll
+                for (int a = 0; a < D; ++a) mm += u[it][1 + a] * u[it][1 + a];
+                const double p = (gam - 1.0) * (u[it][D + 1] - 0.5 * mm * rcp64(u[it][0]));
+                ptile[i] = (PT)(fin && u[it][0] > 0.0 && p > 0.0 ? p : -1.0);
+            }
+        }
+    }
+};
+
+template <int D, int R, int NTHR, typename PT>
+__device__ __forceinline__ void load_tile(const double *__restrict__ U, const Geom &g, const Limiter &lim, int x0,
+                                          int y0, int z0, double (*tile)[MCfg<D, R>::HN], PT *ptile)
+{
+    TileLoad<D, R, NTHR> tl;
+    tl.issue(U, g, x0, y0, z0);
+    tl.commit(U, g, lim, x0, y0, z0, tile, ptile);
 }
+
+// An operand table that every block holds in LDS, N 16-byte slots (a multiple
+// of 64), straight from global memory into LDS (global_load_lds, no registers):
+// wave w of NW copies rows w, w + NW, ... of 64 slots.  Complete once the
+// issuing wave has waited for its vector memory counter.
+template <int N, int NW>
+__device__ __forceinline__ void lds_rows(const uint4 *__restrict__ src, uint4 *dst, int wave, int lane)
+{
+    static_assert(N % 64 == 0, "whole rows of 64 slots");
+    typedef __attribute__((address_space(1))) void *gptr;
+    typedef __attribute__((address_space(3))) void *lptr;
+#pragma unroll
+    for (int r = wave; r < N / 64; r += NW)
+        __builtin_amdgcn_global_load_lds((gptr)(src + r * 64 + lane), (lptr)(dst + r * 64), 16, 0, 0);
+}
+
+// N elements of a small table, copied by NT threads in the same two phases as
+// the tile: load() issues the thread's global loads (past the end it reloads
+// the last element), store() writes what is in range
+template <int N, int NT, typename T>
+struct LdsCopy {
+    static constexpr int NIT = (N + NT - 1) / NT;
+    T r[NIT];
+    __device__ __forceinline__ void load(const T *__restrict__ src)
+    {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) r[it] = src[min((int)threadIdx.x + it * NT, N - 1)];
+    }
+    __device__ __forceinline__ void store(T *dst) const
+    {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = (int)threadIdx.x + it * NT;
+            if (i < N) dst[i] = r[it];
+        }
+    }
+};
 
 // Positivity limiter (section 4) of one cell from the running bounds of its
 // stored face-point increments; both half-waves of the cell call it and get
@@ -743,14 +827,24 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / ((long)nbx * nby));
     const double gam = g.gamma;
 
-    load_tile<D, R, M::NT>(U, g, lim, bx * C::TX - R, by * C::TY - R, D == 3 ? bz * C::TZ - R : 0, tile, ptile);
-    for (int i = threadIdx.x; i < M::A_FULL; i += M::NT) As[i] = Afull[i];
-    for (int i = threadIdx.x; i < M::A_LIN; i += M::NT) Al[i] = Alin[i];
+    // prologue: the tile's loads into registers and the operand tables' loads
+    // straight into LDS all in flight, then the tile's LDS stores (the GELU
+    // chords are computed meanwhile)
+    const int x0 = bx * C::TX - R, y0 = by * C::TY - R, z0 = D == 3 ? bz * C::TZ - R : 0;
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    TileLoad<D, R, M::NT> tl;
+    tl.issue(U, g, x0, y0, z0);
+    lds_rows<M::A_FULL, M::NT / 64>(Afull, As, wv, ln);
+    lds_rows<M::A_LIN, M::NT / 64>(Alin, Al, wv, ln);
+    LdsCopy<GATE ? 97 : 1, M::NT, float> cV;
     if constexpr (GATE) {
-        for (int i = threadIdx.x; i < GateShape<D>::SLOTS; i += M::NT) Wg[i] = ga.w[i];
-        for (int i = threadIdx.x; i < 97; i += M::NT) gvec[i] = ga.vec[i];
+        lds_rows<GateShape<D>::SLOTS, M::NT / 64>(ga.w, Wg, wv, ln);
+        cV.load(ga.vec);
         gelu_table_fill(gvec, threadIdx.x, M::NT);
     }
+    tl.commit(U, g, lim, x0, y0, z0, tile, ptile);
+    if constexpr (GATE) cV.store(gvec);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, hf = lane >> 5;

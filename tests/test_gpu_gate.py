@@ -33,9 +33,10 @@ def K():
 
 
 # The inference evaluates GELU approximately: piecewise linear between nodes
-# 1/64 apart on [-6, 6] (the chord bound h^2/8 max|gelu''|, with
-# max|gelu''| = 2 phi(0) <= 0.798 pinned in test_oracle_mlp) from float32
-# node values, the end chords extended beyond (GELU is 0 or z there to 1e-8).
+# 1/64 apart, the bins centred on k/64 for k = -384 .. 383 (the chord bound
+# h^2/8 max|gelu''|, with max|gelu''| = 2 phi(0) <= 0.798 pinned in
+# test_oracle_mlp) from float32 node values, the end chords extended beyond
+# (GELU is 0 or z there to 1e-8).
 GELU_APPROX = (1.0 / 64.0) ** 2 / 8.0 * 0.7979 + 1e-6
 GELU_SLOPE = 1.13            # max |gelu'|, pinned in test_oracle_mlp
 
