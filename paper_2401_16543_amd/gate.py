@@ -131,9 +131,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dim", type=int, default=2)
     ap.add_argument("--samples", type=int, default=4_000_000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--batch", type=int, default=16384)
-    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr", type=float, default=2e-2)
     ap.add_argument("--out", default=PARAM_DIR)
     args = ap.parse_args()
     from . import kfvm
