@@ -271,7 +271,16 @@ __device__ __forceinline__ double w_component(const double (*tile)[HN], int o, c
 // ----------------------------------------------------------------- Riemann ---
 // HLLC (Toro ch. 10) or HLL, wavespeeds of Batten et al. from Roe averages.
 // Quotients by the densities and wave-speed differences go through rcp64.
-template <int D, int A>
+//
+// WS32 (the split-precision paths): the wave-speed estimates S_L and S_R (sound
+// speeds, Roe averages) in float32 with the hardware square root and
+// reciprocal; the fluxes, S* and the star state stay float64.  Both fluxes
+// equal the physical flux when u_L = u_R whatever S_L and S_R are, and move by
+// a perturbation of either times the jump u_R - u_L: on smooth data a change
+// far below the update's float64 rounding, at a discontinuity a relative 1e-7
+// of the dissipative term.  (Four float64 square roots per point are most of
+// the face-flux kernel's non-FMA work.)
+template <int D, int A, bool WS32 = false>
 __device__ __forceinline__ void riemann(const double *uL, const double *uR, double gam, int hll, double *F)
 {
     constexpr int NV = D + 2, E = D + 1;
@@ -286,22 +295,41 @@ __device__ __forceinline__ void riemann(const double *uL, const double *uR, doub
         qR += uR[1 + b] * vR[b];
     }
     const double pL = (gam - 1.0) * (uL[E] - 0.5 * qL), pR = (gam - 1.0) * (uR[E] - 0.5 * qR);
-    const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
     const double HL = (uL[E] + pL) * irL, HR = (uR[E] + pR) * irR;
-    // Roe weights sqrt(rL) / (sqrt(rL) + sqrt(rR)) and its complement
-    const double sq = sqrt(rR * irL);
-    const double wL = rcp64(1.0 + sq), wR = sq * wL;
-    double qt = 0.0, vtA = 0.0;
+    double SL, SR;
+    if constexpr (WS32) {
+        const float cL = __builtin_amdgcn_sqrtf((float)(gam * pL * irL));
+        const float cR = __builtin_amdgcn_sqrtf((float)(gam * pR * irR));
+        const float sq = __builtin_amdgcn_sqrtf((float)(rR * irL));
+        const float wL = __builtin_amdgcn_rcpf(1.f + sq), wR = sq * wL;
+        float qt = 0.f, vtA = 0.f;
 #pragma unroll
-    for (int b = 0; b < D; ++b) {
-        const double vt = wL * vL[b] + wR * vR[b];
-        qt += vt * vt;
-        if (b == A) vtA = vt;
+        for (int b = 0; b < D; ++b) {
+            const float vt = wL * (float)vL[b] + wR * (float)vR[b];
+            qt += vt * vt;
+            if (b == A) vtA = vt;
+        }
+        const float Ht = wL * (float)HL + wR * (float)HR;
+        const float ct = __builtin_amdgcn_sqrtf((float)(gam - 1.0) * (Ht - 0.5f * qt));
+        SL = (double)fminf((float)vL[A] - cL, vtA - ct);
+        SR = (double)fmaxf((float)vR[A] + cR, vtA + ct);
+    } else {
+        const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
+        // Roe weights sqrt(rL) / (sqrt(rL) + sqrt(rR)) and its complement
+        const double sq = sqrt(rR * irL);
+        const double wL = rcp64(1.0 + sq), wR = sq * wL;
+        double qt = 0.0, vtA = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const double vt = wL * vL[b] + wR * vR[b];
+            qt += vt * vt;
+            if (b == A) vtA = vt;
+        }
+        const double Ht = wL * HL + wR * HR;
+        const double ct = sqrt((gam - 1.0) * (Ht - 0.5 * qt));
+        SL = fmin(vL[A] - cL, vtA - ct);
+        SR = fmax(vR[A] + cR, vtA + ct);
     }
-    const double Ht = wL * HL + wR * HR;
-    const double ct = sqrt((gam - 1.0) * (Ht - 0.5 * qt));
-    const double SL = fmin(vL[A] - cL, vtA - ct);
-    const double SR = fmax(vR[A] + cR, vtA + ct);
     double FL[NV], FR[NV];
     FL[0] = uL[1 + A];
     FR[0] = uR[1 + A];

@@ -1364,7 +1364,7 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
         piR.apply(wR, dR);
 #pragma unroll
         for (int v = 0; v < NV; ++v) { uL[v] = refL[v] + thL * dL[v]; uR[v] = refR[v] + thR * dR[v]; }
-        riemann<D, A>(uL, uR, g.gamma, hll, F);
+        riemann<D, A, true>(uL, uR, g.gamma, hll, F);
         const double w = face_weight<D, R>(gi);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fbar[v] += w * F[v];
@@ -1393,8 +1393,8 @@ __device__ __forceinline__ void boundary_face_flux_mixed(const float *__restrict
 #pragma unroll
         for (int v = 0; v < NV; ++v) in[v] = ref[v] + th * d[v];
         boundary_state<D>(g, A, side, in, out);
-        if (side) riemann<D, A>(in, out, g.gamma, hll, F);
-        else riemann<D, A>(out, in, g.gamma, hll, F);
+        if (side) riemann<D, A, true>(in, out, g.gamma, hll, F);
+        else riemann<D, A, true>(out, in, g.gamma, hll, F);
         const double wt = face_weight<D, R>(gi);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fbar[v] += wt * F[v];
