@@ -364,7 +364,7 @@ __device__ __forceinline__ float pair_blend(float p0, float p1, int hf)
 
 template <int D, int R, int K, bool BF, bool GATE>
 __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
-                                          const uint4 *Al, const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                          const uint4 *Al, const PhiRows<D> &ph, int wbits,
                                           float *__restrict__ inc, uint32_t co, long ncell, bool active, int sw,
                                           const uint4 *Wg, const float *gvec, float thr, uint8_t *__restrict__ fl_out,
                                           const float (&wsc)[3], IncBounds &bnd)
@@ -417,7 +417,7 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
         bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
-    bool use_weno = flags ? at4(flags, (long)K * ncell, co) != 0 : true;
+    bool use_weno = wbits < 0 || ((wbits >> K) & 1) != 0;
     if constexpr (GATE) {
         constexpr int KSG = GateShape<D>::KSG;
         uint4 xb[KSG];
@@ -586,14 +586,14 @@ __device__ __forceinline__ void mixed_var(const double (*tile)[MCfg<D, R>::HN], 
 
 template <int D, int R, bool BF, bool GATE, int... K>
 __device__ __forceinline__ void mixed_all_vars(const double (*tile)[MCfg<D, R>::HN], int lc, int lane, const uint4 *As,
-                                               const uint4 *Al, const PhiRows<D> &ph, const uint8_t *flags,
+                                               const uint4 *Al, const PhiRows<D> &ph, int wbits,
                                                float *inc, uint32_t co, long ncell, bool active, int sw,
                                                const uint4 *Wg, const float *gvec, float thr, uint8_t *fl_out,
                                                const float (&wsc)[3], IncBounds &bnd,
                                                std::integer_sequence<int, K...>)
 {
     ((mixed_var<D, R, K, BF, GATE>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, As, Al,
-                                   ph, flags, inc, co, ncell, active, sw, Wg, gvec, thr, fl_out, wsc, bnd)),
+                                   ph, wbits, inc, co, ncell, active, sw, Wg, gvec, thr, fl_out, wsc, bnd)),
      ...);
 }
 
@@ -856,6 +856,18 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
     const uint32_t co = (uint32_t)cell;
     const int lc = (tx + R) + C::HX * ((ty + R) + C::HY * (D == 3 ? tz + R : 0));
 
+    // precomputed decisions (two-pass indicator, replay), bit K for variable
+    // K, all loaded before the first face-increment store: a wait for a load
+    // issued after the stores would also wait for them (loads and stores share
+    // the vector-memory counter); -1: WENO-AO everywhere
+    int wbits = -1;
+    if (flags) {
+        int m = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) m |= (at4(flags, (long)v * g.ncell, co) != 0 ? 1 : 0) << v;
+        wbits = m;
+    }
+
     double ref[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ref[v] = tile[v][lc];
@@ -874,13 +886,22 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed(
         wsc[1] = (float)(FLAT_REL * sqrt(fabs(gam * pc * ph.inv_rho)));
         wsc[2] = (float)(FLAT_REL * pc);
     }
-    mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, flags, inc, co, g.ncell, active && ok, sw, Wg, gvec,
+    mixed_all_vars<D, R, BF, GATE>(tile, lc, lane, As, Al, ph, wbits, inc, co, g.ncell, active && ok, sw, Wg, gvec,
                                    ga.thr, ga.flags_out, wsc, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
     settle_bounds(bnd);
-    if (lim.on)
-        limiter_factors<D, R>(tile, ptile, lc, hf, ref, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
+    if (lim.on) {
+        // the cell's averages read again from LDS through an opaque index, so
+        // that nothing derived from them (its pressure) is held in registers,
+        // or spilled, across the variables
+        int l2 = lc;
+        asm volatile("" : "+v"(l2));
+        double r2[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r2[v] = tile[v][l2];
+        limiter_factors<D, R>(tile, ptile, lc, hf, r2, active, ok, bnd, lim, g, inc, cell, err, th_rho, th_p);
+    }
     if (active && hf == 0) {
         theta[cell] = th_rho;
         theta[g.ncell + cell] = th_p;
@@ -1024,7 +1045,7 @@ template <int D, int R, int K, bool BF>
 __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>::HN], int lc, int lane,
                                                  const uint4 *__restrict__ Afull, const uint4 *__restrict__ Alin,
                                                  uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
-                                                 const PhiRows<D> &ph, const uint8_t *__restrict__ flags,
+                                                 const PhiRows<D> &ph, int fbits,
                                                  int gbits, uint8_t *__restrict__ fl_out, float *__restrict__ inc,
                                                  uint32_t co, long ncell, bool active, int sw, IncBounds &bnd)
 {
@@ -1067,8 +1088,9 @@ __device__ __forceinline__ void mixed_var_stream(const double (*tile)[MCfg<D, R>
         bl[ks] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 
-    // gate decisions (dilated over the 3^3 block, gbits >= 0), else the flags, else WENO-AO
-    const bool use_weno = gbits >= 0 ? ((gbits >> K) & 1) != 0 : (flags ? at4(flags, (long)K * ncell, co) != 0 : true);
+    // gate decisions (dilated over the 3^3 block, gbits >= 0; recorded in
+    // fl_out), else the precomputed decisions (fbits >= 0), else WENO-AO
+    const bool use_weno = gbits >= 0 ? ((gbits >> K) & 1) != 0 : (fbits >= 0 ? ((fbits >> K) & 1) != 0 : true);
     if (gbits >= 0 && active && hf == 0) at4(fl_out, (long)K * ncell, co) = use_weno ? 1 : 0;
     const uint32_t lo16 = co * 16u + (uint32_t)hf * (uint32_t)(16 * ncell);
     float v2k = 0.f;
@@ -1223,13 +1245,13 @@ template <int D, int R, bool BF, int... K>
 __device__ __forceinline__ void mixed_all_vars_stream(const double (*tile)[MCfg<D, R>::HN], int lc, int lane,
                                                       const uint4 *Afull, const uint4 *Alin,
                                                       uint4 (*buf)[StreamCfg<D, R>::PH * StreamCfg<D, R>::TSL],
-                                                      const PhiRows<D> &ph, const uint8_t *flags, int gbits,
+                                                      const PhiRows<D> &ph, int fbits, int gbits,
                                                       uint8_t *fl_out, float *inc, uint32_t co, long ncell,
                                                       bool active, int sw, IncBounds &bnd,
                                                       std::integer_sequence<int, K...>)
 {
     ((mixed_var_stream<D, R, K, BF>(tile, [&] { int l = lc; asm volatile("" : "+v"(l)); return l; }(), lane, Afull,
-                                    Alin, buf, ph, flags, gbits, fl_out, inc, co, ncell, active, sw, bnd)),
+                                    Alin, buf, ph, fbits, gbits, fl_out, inc, co, ncell, active, sw, bnd)),
      ...);
 }
 
@@ -1294,6 +1316,16 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
                 for (int dx = -1; dx <= 1; ++dx) m |= gtile[lg + dx + GX * (dy + GY * dz)];
         gbits = m;
     }
+    // precomputed decisions (two-pass indicator, replay), bit K for variable
+    // K, loaded before the first face-increment store (see k_recon_mixed);
+    // -1: none
+    int fbits = -1;
+    if (flags) {
+        int m = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) m |= (at4(flags, (long)v * g.ncell, co) != 0 ? 1 : 0) << v;
+        fbits = m;
+    }
 
     double ref[NV];
 #pragma unroll
@@ -1303,7 +1335,7 @@ __global__ __launch_bounds__((MixCfg<D, R>::NT)) void k_recon_mixed_stream(
     PhiRows<D> ph;
     ph.init(ref, gam);
     IncBounds bnd;
-    mixed_all_vars_stream<D, R, BF>(tile, lc, lane, Afull, Alin, buf, ph, flags, gbits, ga.flags_out, inc, co,
+    mixed_all_vars_stream<D, R, BF>(tile, lc, lane, Afull, Alin, buf, ph, fbits, gbits, ga.flags_out, inc, co,
                                     g.ncell, active && ok, sw, bnd, std::make_integer_sequence<int, NV>{});
 
     double th_rho = 1.0, th_p = 1.0;
