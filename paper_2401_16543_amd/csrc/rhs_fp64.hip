@@ -40,6 +40,21 @@ struct FaceBounds {
     double rlo = INFINITY, rhi = -INFINITY, plo = INFINITY, v2 = 0.0;
 };
 
+// Partial sums of a weight row's dot product with the members (members
+// j = 0, 1, .. mod NPS in turn), added pairwise.  A float64 FMA's result reaches
+// the next FMA only after several cycles, and a single chain per row left the
+// VALU waiting on it (3D 256^3, R = 2: 30.3 ms per launch with one chain, 26.8
+// with two, 23.1 with four, 24.1 with eight).  The order differs from the
+// left-to-right sum only in rounding.
+template <int NPS>
+__device__ __forceinline__ double pairwise(const double (&pa)[NPS])
+{
+    static_assert(NPS == 1 || NPS == 2 || NPS == 4, "partial sums combined pairwise");
+    if constexpr (NPS == 4) return (pa[0] + pa[1]) + (pa[2] + pa[3]);
+    else if constexpr (NPS == 2) return pa[0] + pa[1];
+    else return pa[0];
+}
+
 // Reconstruction of variable K of W at every face point of one cell: smoothness
 // indicators (eq. smoothIndic), nonlinear weights (eq. nlinWts) and the WENO-AO
 // blend (eq. wenoAOrec), or the linear S0 value when the gate says so.
@@ -69,12 +84,9 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
     double cq[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) cq[q] = q == 0 ? 1.0 : 0.0;
-    // Each row's dot product with the members runs as four interleaved partial
-    // sums (members j = 0, 1, 2, 3 mod 4) added pairwise at the end: a float64
-    // FMA's result reaches the next FMA only after several cycles, and a single
-    // chain per row left the VALU waiting on it (3D 256^3, R = 2: 30.3 ms per
-    // launch with one chain, 26.8 with two, 23.1 with four, 24.1 with eight).
-    // The order differs from the left-to-right sum only in rounding.
+    // partial sums per row dot product (pairwise): four in 3D; in 2D the extra
+    // registers cost more occupancy than the shorter chains gain
+    constexpr int NPS = D == 3 ? 4 : 1;
     if (use_weno) {
         double beta[NST];
 #pragma unroll
@@ -84,10 +96,10 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
 #pragma unroll
             for (int q = 0; q < NST; ++q) {
                 const double *row = wt + C::st.tab[q] + (NPTS + a) * C::st.nmem[q];
-                double pa[4] = {0.0, 0.0, 0.0, 0.0};
+                double pa[NPS] = {};
 #pragma unroll
-                for (int j = 0; j < C::st.nmem[q]; ++j) pa[j & 3] += row[j] * gv[C::st.mem[q][j]];
-                const double acc = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+                for (int j = 0; j < C::st.nmem[q]; ++j) pa[j % NPS] += row[j] * gv[C::st.mem[q][j]];
+                const double acc = pairwise<NPS>(pa);
                 beta[q] += acc * acc;
             }
         }
@@ -115,10 +127,10 @@ __device__ __forceinline__ void recon_var(const double (*tile)[Cfg<D, R>::HN], i
             v[q] = 0.0;
             if (q == 0 || use_weno) {
                 const double *row = wt + C::st.tab[q] + s * C::st.nmem[q];
-                double pa[4] = {0.0, 0.0, 0.0, 0.0};
+                double pa[NPS] = {};
 #pragma unroll
-                for (int j = 0; j < C::st.nmem[q]; ++j) pa[j & 3] += row[j] * gv[C::st.mem[q][j]];
-                v[q] = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+                for (int j = 0; j < C::st.nmem[q]; ++j) pa[j % NPS] += row[j] * gv[C::st.mem[q][j]];
+                v[q] = pairwise<NPS>(pa);
             }
         }
         double f = v[0];
