@@ -182,9 +182,11 @@ int kfvm_set_stream(kfvm_ctx *ctx, void *hip_stream);
 /* Arithmetic of the weight-apply and smoothness-indicator contractions:
  * KFVM_FP64 (default), or split hi/lo half-precision operands on the matrix
  * cores with float32 accumulation (KFVM_SPLIT_F16, KFVM_SPLIT_BF16); the
- * nonlinear-weight normalisation, the limiter, the Riemann solver and the
- * Runge-Kutta update stay in float64.  The split modes need fewer than 2^27
- * (about 1.3e8, a 512^3 grid) cells (KFVM_ERR_ARG otherwise). */
+ * nonlinear-weight normalisation, the limiter, the Riemann fluxes and the
+ * Runge-Kutta update stay in float64 (the split modes take the Riemann
+ * solver's wave-speed estimates S_L, S_R in float32: the fluxes move by their
+ * rounding times the jump between the two states).  The split modes need fewer
+ * than 2^27 (about 1.3e8, a 512^3 grid) cells (KFVM_ERR_ARG otherwise). */
 int kfvm_set_precision(kfvm_ctx *ctx, int mode);
 
 /* Boundary conditions of one axis (section 5.3: ghost cells filled by them,
