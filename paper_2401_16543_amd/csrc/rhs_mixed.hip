@@ -157,9 +157,12 @@ __device__ __forceinline__ void split_pair(float ya, float yb, uint32_t &hi, uin
         // the mixed-precision FMA reads each FP16 half of hi as an operand and
         // rounds the float32 result y - hi (exact) once to FP16: the same
         // residual as widening hi, subtracting and converting, in one
-        // instruction per value instead of two and a half
+        // instruction per value instead of two and a half.  The compiler does
+        // not see a VALU write in the asm, so the asm itself ends with the two
+        // wait states a matrix-core read of the result may need.
         asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
-            "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+            "s_nop 1"
             : "=&v"(lo)
             : "v"(hi), "v"(ya), "v"(yb));
     }
