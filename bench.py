@@ -27,6 +27,7 @@ METRIC = "cell-updates/sec per RK stage, plain FP64 vs mixed+learned at stated L
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
 HBM_PEAK_GBS = 8000.0
 MFMA_F16_PEAK_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix-core peak
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4   # wave64 VALU instructions per ns: 256 CUs x 4 SIMDs, one per 4 cycles
 
 # (sum of N_q over the stencils, face points, derivative rows, stencils, |S0|)
 _SHAPES = {(2, 2): (38, 8, 5, 6, 13), (2, 3): (82, 12, 9, 6, 29),
@@ -91,6 +92,22 @@ def profiled_traffic(kernel: str, workload: str):
     if not dg or not tb or dg.group(1) != sources_digest(kernel):
         return None
     return float(tb.group(1))
+
+
+def profiled_figure(kernel: str, workload: str, label: str):
+    """A per-launch figure ("VALU instructions per wave", "waves per launch") from
+    the committed rocprofv3 summary of this kernel and workload, or None when
+    there is none or its sources changed since."""
+    import re
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    dg = re.search(r"sources digest: `([0-9a-f]+)`", text)
+    m = re.search(re.escape(label) + r": `([0-9.eE+]+)`", text)
+    if not dg or not m or dg.group(1) != sources_digest(kernel):
+        return None
+    return float(m.group(1))
 
 
 def cpu_baseline(U_host, cfg, budget_s: float):
@@ -272,6 +289,17 @@ def main():
     sbytes = state_bytes_per_cell(d)
     cflops = contraction_flops_per_cell(d, R)
     mix_traffic = profiled_traffic("k_recon_mixed", args.workload)
+    # VALU issue of the headline kernel, the unit that bounds it: counter
+    # figures (rocprofv3 SQ_INSTS_VALU per wave, SQ_WAVES) over the live launch
+    # time, against one wave64 VALU instruction per 4 cycles per SIMD (16 lanes
+    # a cycle) on 1,024 SIMDs at 2.4 GHz
+    vpw = profiled_figure("k_recon_mixed", args.workload, "VALU instructions per wave")
+    wpl = profiled_figure("k_recon_mixed", args.workload, "waves per launch")
+    valu = None
+    if vpw and wpl:
+        got = vpw * wpl / mix_avg / 1e9
+        valu = {"achieved": got, "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-instructions/s",
+                "frac": got / VALU_ISSUE_PEAK_G, "valu_per_wave": vpw, "waves_per_launch": wpl}
     out = {
         "metric": METRIC, "value": ncell * stages / t_mix, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_mix / args.steps * 1e3,
@@ -298,13 +326,17 @@ def main():
                      "traffic": mix_traffic,
                      "traffic_ratio": mix_traffic / (sbytes * ncell) if mix_traffic else None,
                      "flops_per_cell": cflops, "alg_bytes_per_cell": sbytes, "avg_launch_ms": mix_avg * 1e3,
+                     "valu_issue": valu,
                      "hbm_achieved_gbs": sbytes * ncell / mix_avg / 1e9,
                      "hbm_frac": sbytes * ncell / mix_avg / 1e9 / HBM_PEAK_GBS,
                      "note": "achieved = the sparse weight-apply and smoothness-indicator contraction (every "
                              "stencil row, every variable, no hi/lo split) per launch over the mean launch time, "
                              "against the dense fp16 matrix-core peak; hbm_* = the stage's state traffic "
                              "(3 float64 averages per variable) over the same time; traffic = measured HBM bytes "
-                             "per launch (rocprofv3 counters), traffic_ratio = traffic / state bytes"},
+                             "per launch (rocprofv3 counters), traffic_ratio = traffic / state bytes; "
+                             "valu_issue = VALU wave-instructions issued per second (SQ_INSTS_VALU per wave x "
+                             "waves per launch from the same counter summary, over the mean launch time) against "
+                             "1,024 SIMDs issuing one every 4 cycles at 2.4 GHz: the unit that bounds this kernel"},
         "kernels_ms_per_launch": per_launch(kt_mix),
         "plain_fp64": {"value": ncell * stages / t_plain, "ms_per_step": t_plain / args.steps * 1e3,
                        "dtype": "f64", "roofline": roof(kt_plain), "kernels_ms_per_launch": per_launch(kt_plain)},
