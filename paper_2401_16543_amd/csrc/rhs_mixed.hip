@@ -1381,16 +1381,39 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
             gR[v] = *reinterpret_cast<const float4 *>(incR + inc_index((2 * A + 0) * NG, v, NV, g.ncell));
         }
     }
-    constexpr int UNROLL = VEC ? NG : 1;
+    // nine points per face (3D R = 3): each side's points lie in three 16-byte
+    // groups of four (inc_index); a group is loaded, one vector per variable,
+    // at the first point that falls in it, so one group per side is live
+    constexpr bool GRP = NG > 4;
+    float4 cL[GRP ? NV : 1], cR[GRP ? NV : 1];
+    constexpr int UNROLL = VEC || GRP ? NG : 1;
 #pragma unroll UNROLL
     for (int gi = 0; gi < NG; ++gi) {
         double wL[NV], wR[NV], dL[NV], dR[NV], uL[NV], uR[NV], F[NV];
+        if constexpr (GRP) {
+            const int tL = (2 * A + 1) * NG + gi, tR = (2 * A + 0) * NG + gi;
+            if (gi == 0 || (tL & 3) == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    cL[v] = *reinterpret_cast<const float4 *>(incL + inc_index(tL & ~3, v, NV, g.ncell));
+            }
+            if (gi == 0 || (tR & 3) == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    cR[v] = *reinterpret_cast<const float4 *>(incR + inc_index(tR & ~3, v, NV, g.ncell));
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                wL[v] = (double)cL[v][tL & 3];
+                wR[v] = (double)cR[v][tR & 3];
+            }
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if constexpr (VEC) {
                 wL[v] = (double)gL[v][gi];
                 wR[v] = (double)gR[v][gi];
-            } else {
+            } else if constexpr (!GRP) {
                 wL[v] = (double)incL[inc_index((2 * A + 1) * NG + gi, v, NV, g.ncell)];
                 wR[v] = (double)incR[inc_index((2 * A + 0) * NG + gi, v, NV, g.ncell)];
             }
