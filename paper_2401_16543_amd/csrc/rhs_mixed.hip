@@ -1381,10 +1381,10 @@ __device__ __forceinline__ void lower_face_flux_mixed(const double *__restrict__
             gR[v] = *reinterpret_cast<const float4 *>(incR + inc_index((2 * A + 0) * NG, v, NV, g.ncell));
         }
     }
-    // nine points per face (3D R = 3): each side's points lie in three 16-byte
+    // other point counts (2D; 3D R = 3: nine): each side's points lie in 16-byte
     // groups of four (inc_index); a group is loaded, one vector per variable,
     // at the first point that falls in it, so one group per side is live
-    constexpr bool GRP = NG > 4;
+    constexpr bool GRP = NG != 4;
     float4 cL[GRP ? NV : 1], cR[GRP ? NV : 1];
     constexpr int UNROLL = VEC || GRP ? NG : 1;
 #pragma unroll UNROLL
